@@ -1,0 +1,1056 @@
+/*
+ * ORACLE — test infrastructure, not part of the product.
+ *
+ * A plain, slow, scalar CPU implementation of one two-stage fourth-order (S2O4) time step of the
+ * 2-D Euler finite-volume scheme with the hybrid DF / WENO-AO reconstruction of
+ *   H. Zhang, X. Ji, K. Xu, "A robustness-enhanced reconstruction based on discontinuity feedback
+ *   factor for high-order finite volume scheme", arXiv:2402.10914.
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header, table or helper with the HIP implementation; the two are written independently
+ * from the paper.  Arithmetic is FP64 (or forward-mode dual numbers over FP64 for tangents).
+ *
+ * Structure follows Algorithm 1 of the paper: time increment from the CFL condition, then per
+ * stage: boundary condition (explicit ghost arrays), characteristic variables, normal
+ * reconstruction, tangential reconstruction at the Gauss points, interface fluxes and their time
+ * derivatives, cell update; finally the DF update.  Where the paper is silent or garbled the
+ * readings documented in the design notes are taken; each is named where it is used:
+ *   (R1) characteristic basis = eigenvectors of the normal flux Jacobian at the arithmetic mean of
+ *        the two cells adjacent to the interface; the tangential sweep re-projects the
+ *        conservative line values of the neighbouring interface segments onto the basis of the
+ *        target segment.
+ *   (R2) epsilon of the WENO-Z weights is a parameter (default 1e-6).
+ *   (R3) dt = CFL / max_cells max((|U|+c)/dx, (|V|+c)/dy).
+ *   (R5) alpha^{n+1} is built from the Gauss-point states of the second stage.
+ *   (R6) alpha^n drives the switch in both stages.
+ *   (R7) physical collision time 0 (Euler); tau_n only inside exp(-t/tau_n).
+ *   (R8) LF + S2O4: dF/dt by the Cauchy-Kovalevskaya procedure, LF speed frozen.
+ *   (R9) the normal derivative at a Gauss point is the line value of the normal sweep.
+ *   (R13) transmissive boundary = copy of the nearest interior cell.
+ *   (R24) second-stage GKS integrals use the same dt and tau_n formula as the first stage.
+ * Functions that are not pinned by a closed form, a special case or brute force say so.
+ */
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+namespace dfo {
+
+/* ------------------------------------------------------------------------------------------ */
+/* Scalar types: double, and forward-mode dual numbers Dual<T> (value + one tangent).          */
+/* ------------------------------------------------------------------------------------------ */
+template <class T>
+struct Dual {
+  T v, d;
+  Dual() : v(0.0), d(0.0) {}
+  template <class U, class = typename std::enable_if<std::is_arithmetic<U>::value>::type>
+  Dual(U x) : v(static_cast<double>(x)), d(0.0) {}
+  Dual(const T& a, const T& b) : v(a), d(b) {}
+};
+
+inline double val(double x) { return x; }
+template <class T>
+double val(const Dual<T>& x) { return val(x.v); }
+
+template <class T> Dual<T> operator+(const Dual<T>& a, const Dual<T>& b) { return Dual<T>(a.v + b.v, a.d + b.d); }
+template <class T> Dual<T> operator-(const Dual<T>& a, const Dual<T>& b) { return Dual<T>(a.v - b.v, a.d - b.d); }
+template <class T> Dual<T> operator-(const Dual<T>& a) { return Dual<T>(-a.v, -a.d); }
+template <class T> Dual<T> operator*(const Dual<T>& a, const Dual<T>& b) { return Dual<T>(a.v * b.v, a.d * b.v + a.v * b.d); }
+template <class T> Dual<T> operator/(const Dual<T>& a, const Dual<T>& b) {
+  T q = a.v / b.v;
+  return Dual<T>(q, (a.d - q * b.d) / b.v);
+}
+template <class T> Dual<T> operator+(double s, const Dual<T>& a) { return Dual<T>(s + a.v, a.d); }
+template <class T> Dual<T> operator+(const Dual<T>& a, double s) { return Dual<T>(a.v + s, a.d); }
+template <class T> Dual<T> operator-(double s, const Dual<T>& a) { return Dual<T>(s - a.v, -a.d); }
+template <class T> Dual<T> operator-(const Dual<T>& a, double s) { return Dual<T>(a.v - s, a.d); }
+template <class T> Dual<T> operator*(double s, const Dual<T>& a) { return Dual<T>(s * a.v, s * a.d); }
+template <class T> Dual<T> operator*(const Dual<T>& a, double s) { return Dual<T>(a.v * s, a.d * s); }
+template <class T> Dual<T> operator/(const Dual<T>& a, double s) { return Dual<T>(a.v / s, a.d / s); }
+template <class T> Dual<T> operator/(double s, const Dual<T>& a) { return Dual<T>(s, 0.0) / a; }
+template <class T> Dual<T>& operator+=(Dual<T>& a, const Dual<T>& b) { a = a + b; return a; }
+template <class T> Dual<T>& operator-=(Dual<T>& a, const Dual<T>& b) { a = a - b; return a; }
+template <class T> Dual<T>& operator*=(Dual<T>& a, const Dual<T>& b) { a = a * b; return a; }
+
+inline double msqrt(double x) { return std::sqrt(x); }
+inline double mexp(double x) { return std::exp(x); }
+inline double merfc(double x) { return std::erfc(x); }
+template <class T> Dual<T> msqrt(const Dual<T>& a) { T s = msqrt(a.v); return Dual<T>(s, a.d / (2.0 * s)); }
+template <class T> Dual<T> mexp(const Dual<T>& a) { T e = mexp(a.v); return Dual<T>(e, e * a.d); }
+template <class T> Dual<T> merfc(const Dual<T>& a) {
+  const double two_over_sqrtpi = 1.1283791670955126;  /* 2/sqrt(pi) */
+  return Dual<T>(merfc(a.v), -two_over_sqrtpi * mexp(-(a.v * a.v)) * a.d);
+}
+/* |x| with the subgradient convention sign(0) = 0. */
+template <class T> T mabs(const T& a) {
+  double x = val(a);
+  if (x > 0) return a;
+  if (x < 0) return -a;
+  return a * 0.0;
+}
+/* max(a, b) routes to a when a >= b. */
+template <class T> T mmax(const T& a, const T& b) { return val(a) >= val(b) ? a : b; }
+template <class T> T sq(const T& a) { return a * a; }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Problem description.                                                                        */
+/* ------------------------------------------------------------------------------------------ */
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+enum { FLUX_LF = 0, FLUX_GKS = 1 };
+
+struct Grid {
+  int32_t nx, ny;
+  double dx, dy;
+  int32_t bc_x, bc_y;
+};
+
+struct Params {
+  double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
+  int32_t flux;
+};
+
+/* ------------------------------------------------------------------------------------------ */
+/* Small dense linear algebra (Gauss-Jordan with partial pivoting).                            */
+/* ------------------------------------------------------------------------------------------ */
+template <class T>
+static void solve_linear(int n, const T* A_in, const T* b_in, T* x) {
+  /* Solves A x = b for one right-hand side; A is n x n row-major. */
+  T A[64], b[8];
+  for (int i = 0; i < n * n; ++i) A[i] = A_in[i];
+  for (int i = 0; i < n; ++i) b[i] = b_in[i];
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(val(A[r * n + c])) > std::fabs(val(A[p * n + c]))) p = r;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[p * n + k]);
+      std::swap(b[c], b[p]);
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      T f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] = A[r * n + k] - f * A[c * n + k];
+      b[r] = b[r] - f * b[c];
+    }
+  }
+  for (int i = 0; i < n; ++i) x[i] = b[i] / A[i * n + i];
+}
+
+template <class T>
+static void invert(int n, const T* A, T* Ainv) {
+  T e[8], col[8];
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) e[i] = T(i == j ? 1.0 : 0.0);
+    solve_linear(n, A, e, col);
+    for (int i = 0; i < n; ++i) Ainv[i * n + j] = col[i];
+  }
+}
+
+template <class T>
+static void matvec4(const T* M, const T* x, T* y) {
+  for (int i = 0; i < 4; ++i) {
+    T s = M[i * 4 + 0] * x[0];
+    for (int k = 1; k < 4; ++k) s = s + M[i * 4 + k] * x[k];
+    y[i] = s;
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Section 3.1: candidate polynomials of WENO-AO(5,3).                                         */
+/* The coordinate is xi = (x - x_{i+1/2}) / dx, so the target cell i is [-1, 0] and the cell    */
+/* with offset o is [o-1, o].  Each candidate is the polynomial whose averages over its        */
+/* sub-stencil cells equal the given cell averages; the oracle obtains it by solving that      */
+/* small cell-average fitting system once (the paper prints the resulting coefficients; the    */
+/* tests compare the two).                                                                     */
+/* ------------------------------------------------------------------------------------------ */
+struct Candidates {
+  /* coef[k][n][m]: coefficient of xi^n in p_k as a linear combination of Q_{i-2+m}. */
+  double coef[4][5][5];
+  int deg[4];
+};
+
+static Candidates build_candidates() {
+  Candidates C;
+  std::memset(&C, 0, sizeof(C));
+  const int first[4] = {-2, -1, 0, -2};
+  const int ncell[4] = {3, 3, 3, 5};
+  for (int k = 0; k < 4; ++k) {
+    int n = ncell[k];
+    C.deg[k] = n - 1;
+    double V[25], Vinv[25];
+    for (int r = 0; r < n; ++r) {
+      int o = first[k] + r;
+      for (int p = 0; p < n; ++p) /* average of xi^p over [o-1, o] */
+        V[r * n + p] = (std::pow((double)o, p + 1) - std::pow((double)(o - 1), p + 1)) / (p + 1);
+    }
+    invert(n, V, Vinv);
+    for (int p = 0; p < n; ++p)
+      for (int r = 0; r < n; ++r) C.coef[k][p][first[k] + r + 2] = Vinv[p * n + r];
+  }
+  return C;
+}
+
+static const Candidates& candidates() {
+  static const Candidates C = build_candidates();
+  return C;
+}
+
+/* Polynomial helpers; coefficients are in powers of xi, degree <= 4. */
+template <class T>
+static T poly_eval(const T* c, int deg, double xi) {
+  T s = c[deg];
+  for (int n = deg - 1; n >= 0; --n) s = s * xi + c[n];
+  return s;
+}
+template <class T>
+static T poly_deriv_eval(const T* c, int deg, double xi) {
+  if (deg == 0) return T(0.0);
+  T s = c[deg] * (double)deg;
+  for (int n = deg - 1; n >= 1; --n) s = s * xi + c[n] * (double)n;
+  return s;
+}
+
+/* Eq. (38): beta = sum_{q=1}^{deg} dx^{2q-1} int_cell (d^q p / dx^q)^2 dx, i.e. in xi units
+ * sum_q int_{-1}^{0} (p^{(q)}(xi))^2 dxi, integrated exactly term by term. */
+template <class T>
+static T smoothness(const T* c, int deg) {
+  T beta = T(0.0);
+  T d[5];
+  for (int n = 0; n <= deg; ++n) d[n] = c[n];
+  int dd = deg;
+  for (int q = 1; q <= deg; ++q) {
+    /* differentiate once */
+    for (int n = 0; n < dd; ++n) d[n] = d[n + 1] * (double)(n + 1);
+    dd -= 1;
+    /* int_{-1}^{0} xi^m dxi = (-1)^m / (m + 1) */
+    for (int a = 0; a <= dd; ++a)
+      for (int b = 0; b <= dd; ++b) {
+        int m = a + b;
+        double w = ((m % 2) ? -1.0 : 1.0) / (m + 1);
+        beta = beta + d[a] * d[b] * w;
+      }
+  }
+  return beta;
+}
+
+/* WENO-AO(5,3) with WENO-Z weights (Section 3.1, eqs. (37)-(38)): returns the coefficients of
+ * P(xi) on the target cell for the five averages Q[0..4] = Q_{i-2..i+2}. */
+template <class T>
+static void weno_ao_poly(const T* Q, const Params& prm, T* P) {
+  const Candidates& C = candidates();
+  T p[4][5];
+  for (int k = 0; k < 4; ++k)
+    for (int n = 0; n < 5; ++n) {
+      T s = T(0.0);
+      for (int m = 0; m < 5; ++m)
+        if (C.coef[k][n][m] != 0.0) s = s + C.coef[k][n][m] * Q[m];
+      p[k][n] = s;
+    }
+  /* linear weights */
+  double dH = prm.d_h, dL = prm.d_l;
+  double d[4];
+  d[3] = dH;
+  d[0] = (1.0 - dH) * (1.0 - dL) / 2.0;
+  d[1] = (1.0 - dH) * dL;
+  d[2] = d[0];
+  T beta[4];
+  for (int k = 0; k < 4; ++k) beta[k] = smoothness(p[k], C.deg[k]);
+  T tau = (mabs(beta[3] - beta[0]) + mabs(beta[3] - beta[1]) + mabs(beta[3] - beta[2])) / 3.0;
+  T w[4], wsum = T(0.0);
+  for (int k = 0; k < 4; ++k) {
+    w[k] = d[k] * (1.0 + sq(tau / (beta[k] + prm.eps_weno)));
+    wsum = wsum + w[k];
+  }
+  T wb[4];
+  for (int k = 0; k < 4; ++k) wb[k] = w[k] / wsum;
+  for (int n = 0; n < 5; ++n) {
+    T hi = p[3][n] / d[3];
+    for (int k = 0; k < 3; ++k) hi = hi - (d[k] / d[3]) * p[k][n];
+    T s = wb[3] * hi;
+    for (int k = 0; k < 3; ++k) s = s + wb[k] * p[k][n];
+    P[n] = s;
+  }
+}
+
+/* Section 3.3: the hybrid reconstruction of one cell.  a3 = (alpha_{i-1}, alpha_i, alpha_{i+1}).
+ * If max(a3) < alpha_thres (strict, eq. (34)) the DF-weighted zero-mean quadratic
+ *   Q_i + alpha_i [ (Q_{i+1}-Q_i)/dx (x - x0) + (Q_{i-1}/2 - Q_i + Q_{i+1}/2)/dx^2 (x^2 - x1) ],
+ * x0 = -dx/2, x1 = dx^2/3, replaces WENO-AO; otherwise WENO-AO.  Coefficients in xi. */
+template <class T>
+static void hybrid_poly(const T* Q, const T* a3, const Params& prm, T* P) {
+  T amax = mmax(mmax(a3[0], a3[1]), a3[2]);
+  if (val(amax) < prm.alpha_thres) {
+    const T& al = a3[1];
+    T slope = Q[3] - Q[2];
+    T curv = 0.5 * Q[1] - Q[2] + 0.5 * Q[3];
+    const double x0 = -0.5, x1 = 1.0 / 3.0;
+    P[0] = Q[2] + al * (-(slope * x0) - curv * x1);
+    P[1] = al * slope;
+    P[2] = al * curv;
+    P[3] = T(0.0);
+    P[4] = T(0.0);
+  } else {
+    weno_ao_poly(Q, prm, P);
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Section 2.1: local frame.  theta = 0 for x-interfaces, pi/2 for y-interfaces (exact entries). */
+/* ------------------------------------------------------------------------------------------ */
+struct Frame {
+  double c, s; /* cos(theta), sin(theta) */
+};
+static const Frame kFrame[2] = {{1.0, 0.0}, {0.0, 1.0}};
+
+template <class T>
+static void rotate(const Frame& f, const T* W, T* Wt) { /* W~ = T W */
+  Wt[0] = W[0];
+  Wt[1] = f.c * W[1] + f.s * W[2];
+  Wt[2] = -f.s * W[1] + f.c * W[2];
+  Wt[3] = W[3];
+}
+template <class T>
+static void rotate_back(const Frame& f, const T* Wt, T* W) { /* W = T^{-1} W~ */
+  W[0] = Wt[0];
+  W[1] = f.c * Wt[1] - f.s * Wt[2];
+  W[2] = f.s * Wt[1] + f.c * Wt[2];
+  W[3] = Wt[3];
+}
+
+template <class T>
+static T pressure(const T* W, double gamma) {
+  return (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+}
+
+/* Eigenvectors of the normal flux Jacobian (R1): right eigenvectors built in the local frame
+ * (columns (1,u-c,v,H-uc), (1,u,v,(u^2+v^2)/2), (0,0,1,v), (1,u+c,v,H+uc)), rotated back to the
+ * global frame; the left eigenvectors are the numerical inverse. */
+template <class T>
+static void char_basis(const Frame& f, const T* Wmean, double gamma, T* R, T* L) {
+  T Wl[4];
+  rotate(f, Wmean, Wl);
+  T rho = Wl[0], u = Wl[1] / rho, v = Wl[2] / rho;
+  T p = pressure(Wl, gamma);
+  T c = msqrt(gamma * p / rho);
+  T H = (Wl[3] + p) / rho;
+  T Rl[4][4] = {{T(1.0), T(1.0), T(0.0), T(1.0)},
+                {u - c, u, T(0.0), u + c},
+                {v, v, T(1.0), v},
+                {H - u * c, 0.5 * (u * u + v * v), v, H + u * c}};
+  for (int col = 0; col < 4; ++col) {
+    T cl[4] = {Rl[0][col], Rl[1][col], Rl[2][col], Rl[3][col]}, cg[4];
+    rotate_back(f, cl, cg);
+    for (int r = 0; r < 4; ++r) R[r * 4 + col] = cg[r];
+  }
+  invert(4, R, L);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Section 2.3: Euler fluxes in the local frame and the Lax-Friedrichs flux.                   */
+/* ------------------------------------------------------------------------------------------ */
+template <class S>
+static void euler_flux_x(const S* W, double gamma, S* F) {
+  S u = W[1] / W[0];
+  S p = (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+  F[0] = W[1];
+  F[1] = W[1] * u + p;
+  F[2] = W[2] * u;
+  F[3] = u * (W[3] + p);
+}
+template <class S>
+static void euler_flux_y(const S* W, double gamma, S* G) {
+  S v = W[2] / W[0];
+  S p = (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+  G[0] = W[2];
+  G[1] = W[1] * v;
+  G[2] = W[2] * v + p;
+  G[3] = v * (W[3] + p);
+}
+
+/* Directional derivative dF(W)[dW] of a flux by forward-mode dual numbers. */
+template <class T, bool Y>
+static void flux_jvp(const T* W, const T* dW, double gamma, T* out) {
+  Dual<T> w[4], F[4];
+  for (int k = 0; k < 4; ++k) w[k] = Dual<T>(W[k], dW[k]);
+  if (Y) euler_flux_y(w, gamma, F);
+  else euler_flux_x(w, gamma, F);
+  for (int k = 0; k < 4; ++k) out[k] = F[k].d;
+}
+
+/* (R8) Cauchy-Kovalevskaya: W_t = -(A W_x + B W_y), F_t = A W_t, with A = dF/dW, B = dG/dW. */
+template <class T>
+static void ck_time_derivative(const T* W, const T* Wx, const T* Wy, double gamma, T* Wt, T* Ft) {
+  T a[4], b[4];
+  flux_jvp<T, false>(W, Wx, gamma, a);
+  flux_jvp<T, true>(W, Wy, gamma, b);
+  for (int k = 0; k < 4; ++k) Wt[k] = -(a[k] + b[k]);
+  flux_jvp<T, false>(W, Wt, gamma, Ft);
+}
+
+/* LF flux (Section 2.3) and its time derivative (R8), local frame. */
+template <class T>
+static void lf_flux(const T* Wl, const T* Wlx, const T* Wly, const T* Wr, const T* Wrx,
+                    const T* Wry, double gamma, T* F, T* Ft) {
+  T Fl[4], Fr[4];
+  euler_flux_x(Wl, gamma, Fl);
+  euler_flux_x(Wr, gamma, Fr);
+  T cl = msqrt(gamma * pressure(Wl, gamma) / Wl[0]);
+  T cr = msqrt(gamma * pressure(Wr, gamma) / Wr[0]);
+  T s = mmax(mabs(Wl[1] / Wl[0]) + cl, mabs(Wr[1] / Wr[0]) + cr);
+  T Wtl[4], Ftl[4], Wtr[4], Ftr[4];
+  ck_time_derivative(Wl, Wlx, Wly, gamma, Wtl, Ftl);
+  ck_time_derivative(Wr, Wrx, Wry, gamma, Wtr, Ftr);
+  for (int k = 0; k < 4; ++k) {
+    F[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * s * (Wr[k] - Wl[k]);
+    Ft[k] = 0.5 * (Ftl[k] + Ftr[k]) - 0.5 * s * (Wtr[k] - Wtl[k]);
+  }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Section 2.2 / 3.4: the gas-kinetic flux.                                                   */
+/* Polynomials in the particle velocity (u, v) and internal energy xi^2 are kept as lists of  */
+/* monomials u^a v^b (xi^2)^c; a moment <.> of a Maxwellian factorises into <u^a><v^b><xi^2c>. */
+/* ------------------------------------------------------------------------------------------ */
+template <class T>
+struct Term {
+  int a, b, c;
+  T k;
+};
+template <class T>
+struct KPoly {
+  Term<T> t[48];
+  int n = 0;
+  void add(int a, int b, int c, const T& k) { t[n++] = Term<T>{a, b, c, k}; }
+};
+
+/* psi = (1, u, v, (u^2 + v^2 + xi^2)/2) */
+template <class T>
+static KPoly<T> psi(int k) {
+  KPoly<T> P;
+  if (k == 0) P.add(0, 0, 0, T(1.0));
+  if (k == 1) P.add(1, 0, 0, T(1.0));
+  if (k == 2) P.add(0, 1, 0, T(1.0));
+  if (k == 3) {
+    P.add(2, 0, 0, T(0.5));
+    P.add(0, 2, 0, T(0.5));
+    P.add(0, 0, 1, T(0.5));
+  }
+  return P;
+}
+/* a . psi = a1 + a2 u + a3 v + a4 (u^2 + v^2 + xi^2)/2 */
+template <class T>
+static KPoly<T> dot_psi(const T* a) {
+  KPoly<T> P;
+  P.add(0, 0, 0, a[0]);
+  P.add(1, 0, 0, a[1]);
+  P.add(0, 1, 0, a[2]);
+  P.add(2, 0, 0, 0.5 * a[3]);
+  P.add(0, 2, 0, 0.5 * a[3]);
+  P.add(0, 0, 1, 0.5 * a[3]);
+  return P;
+}
+template <class T>
+static KPoly<T> mul(const KPoly<T>& A, const KPoly<T>& B) {
+  KPoly<T> P;
+  for (int i = 0; i < A.n; ++i)
+    for (int j = 0; j < B.n; ++j)
+      P.add(A.t[i].a + B.t[j].a, A.t[i].b + B.t[j].b, A.t[i].c + B.t[j].c, A.t[i].k * B.t[j].k);
+  return P;
+}
+template <class T>
+static KPoly<T> mono(int a, int b) {
+  KPoly<T> P;
+  P.add(a, b, 0, T(1.0));
+  return P;
+}
+
+enum { SPACE_FULL = 0, SPACE_POS = 1, SPACE_NEG = 2 };
+constexpr int kMaxU = 10;
+
+/* Moments of the normalised Maxwellian (lambda/pi)^{(K+2)/2} exp(-lambda((u-U)^2+(v-V)^2+xi^2)):
+ *   <u^0> = 1, <u^1> = U, <u^{n+2}> = U <u^{n+1}> + (n+1)/(2 lambda) <u^n>   (full space),
+ *   <u^0>_{>0} = erfc(-sqrt(lambda) U)/2, <u^1>_{>0} = U <u^0>_{>0} + exp(-lambda U^2)/(2 sqrt(pi lambda)),
+ *   <u^0>_{<0} = erfc( sqrt(lambda) U)/2, <u^1>_{<0} = U <u^0>_{<0} - exp(-lambda U^2)/(2 sqrt(pi lambda)),
+ * with the same recursion for the half spaces, and
+ *   <xi^0> = 1, <xi^2> = K/(2 lambda), <xi^4> = (K^2 + 2K)/(4 lambda^2), <xi^6> = K(K+2)(K+4)/(8 lambda^3). */
+template <class T>
+static void u_moments(const T& U, const T& lam, int space, T* M) {
+  const double pi = 3.14159265358979323846;
+  if (space == SPACE_FULL) {
+    M[0] = T(1.0);
+    M[1] = U;
+  } else {
+    T sl = msqrt(lam);
+    T e = mexp(-(lam * U * U)) / (2.0 * msqrt(pi * lam));
+    if (space == SPACE_POS) {
+      M[0] = 0.5 * merfc(-(sl * U));
+      M[1] = U * M[0] + e;
+    } else {
+      M[0] = 0.5 * merfc(sl * U);
+      M[1] = U * M[0] - e;
+    }
+  }
+  for (int n = 0; n + 2 <= kMaxU; ++n) M[n + 2] = U * M[n + 1] + ((double)(n + 1)) / (2.0 * lam) * M[n];
+}
+
+template <class T>
+struct Maxwellian {
+  T rho, U, V, lam;
+  T mu[3][kMaxU + 1]; /* u-moments: full, u>0, u<0 */
+  T mv[kMaxU + 1];
+  T mxi[4];
+};
+
+template <class T>
+static Maxwellian<T> maxwellian(const T* W, double gamma) {
+  Maxwellian<T> g;
+  double K = (4.0 - 2.0 * gamma) / (gamma - 1.0);
+  g.rho = W[0];
+  g.U = W[1] / W[0];
+  g.V = W[2] / W[0];
+  T p = pressure(W, gamma);
+  g.lam = W[0] / (2.0 * p);
+  for (int s = 0; s < 3; ++s) u_moments(g.U, g.lam, s, g.mu[s]);
+  u_moments(g.V, g.lam, SPACE_FULL, g.mv);
+  g.mxi[0] = T(1.0);
+  g.mxi[1] = K / (2.0 * g.lam);
+  g.mxi[2] = (K * K + 2.0 * K) / (4.0 * g.lam * g.lam);
+  g.mxi[3] = K * (K + 2.0) * (K + 4.0) / (8.0 * g.lam * g.lam * g.lam);
+  return g;
+}
+
+template <class T>
+static T moment(const Maxwellian<T>& g, int space, const KPoly<T>& P) {
+  T s = T(0.0);
+  for (int i = 0; i < P.n; ++i) s = s + P.t[i].k * g.mu[space][P.t[i].a] * g.mv[P.t[i].b] * g.mxi[P.t[i].c];
+  return s;
+}
+
+/* Micro-slope a of a Maxwellian from a macroscopic derivative dW: solves <(a.psi) psi> = dW/rho. */
+template <class T>
+static void micro_slope(const Maxwellian<T>& g, const T* dW, T* a) {
+  T M[16], b[4];
+  for (int k = 0; k < 4; ++k) {
+    for (int l = 0; l < 4; ++l) M[k * 4 + l] = moment(g, SPACE_FULL, mul(psi<T>(k), psi<T>(l)));
+    b[k] = dW[k] / g.rho;
+  }
+  solve_linear(4, M, b, a);
+}
+
+/* GKS flux at one Gauss point, local frame (x normal).  Inputs: left/right states and their
+ * normal (x) and tangential (y) derivatives; dt of the step; C1, C2 of tau_n. */
+template <class T>
+static void gks_flux(const T* Wl, const T* Wlx, const T* Wly, const T* Wr, const T* Wrx,
+                     const T* Wry, double gamma, double dt, double C1, double C2, T* F, T* Ft) {
+  Maxwellian<T> gl = maxwellian(Wl, gamma), gr = maxwellian(Wr, gamma);
+  T al[4], bl[4], ar[4], br[4];
+  micro_slope(gl, Wlx, al);
+  micro_slope(gl, Wly, bl);
+  micro_slope(gr, Wrx, ar);
+  micro_slope(gr, Wry, br);
+  /* Section 3.4: equilibrium state and its slopes by kinetic weighting (R10: at the Gauss point). */
+  T Wc[4], Wcx[4], Wcy[4];
+  KPoly<T> apl = dot_psi(al), bpl = dot_psi(bl), apr = dot_psi(ar), bpr = dot_psi(br);
+  for (int k = 0; k < 4; ++k) {
+    KPoly<T> pk = psi<T>(k);
+    Wc[k] = gl.rho * moment(gl, SPACE_POS, pk) + gr.rho * moment(gr, SPACE_NEG, pk);
+    Wcx[k] = gl.rho * moment(gl, SPACE_POS, mul(apl, pk)) + gr.rho * moment(gr, SPACE_NEG, mul(apr, pk));
+    Wcy[k] = gl.rho * moment(gl, SPACE_POS, mul(bpl, pk)) + gr.rho * moment(gr, SPACE_NEG, mul(bpr, pk));
+  }
+  Maxwellian<T> gc = maxwellian(Wc, gamma);
+  T ac[4], bc[4], Ac[4];
+  micro_slope(gc, Wcx, ac);
+  micro_slope(gc, Wcy, bc);
+  KPoly<T> apc = dot_psi(ac), bpc = dot_psi(bc);
+  KPoly<T> u1 = mono<T>(1, 0), v1 = mono<T>(0, 1);
+  KPoly<T> transport_c = mul(apc, u1); /* (a.psi) u + (b.psi) v, concatenated */
+  {
+    KPoly<T> bv = mul(bpc, v1);
+    for (int i = 0; i < bv.n; ++i) transport_c.t[transport_c.n++] = bv.t[i];
+  }
+  /* compatibility condition: <(A.psi) psi> = -<((a.psi) u + (b.psi) v) psi> (per unit density) */
+  {
+    T rhs[4];
+    for (int k = 0; k < 4; ++k) rhs[k] = -(gc.rho * moment(gc, SPACE_FULL, mul(transport_c, psi<T>(k))));
+    micro_slope(gc, rhs, Ac);
+  }
+  KPoly<T> Apc = dot_psi(Ac);
+  KPoly<T> transport_l = mul(apl, u1), transport_r = mul(apr, u1);
+  {
+    KPoly<T> bv = mul(bpl, v1);
+    for (int i = 0; i < bv.n; ++i) transport_l.t[transport_l.n++] = bv.t[i];
+    KPoly<T> bw = mul(bpr, v1);
+    for (int i = 0; i < bw.n; ++i) transport_r.t[transport_r.n++] = bw.t[i];
+  }
+  /* Fluxes of the pieces of f (R7: physical tau = 0 outside the exponential). */
+  T Fc[4], Mac[4], MAc[4], Flr[4], Malr[4];
+  for (int k = 0; k < 4; ++k) {
+    KPoly<T> upk = mul(u1, psi<T>(k));
+    Fc[k] = gc.rho * moment(gc, SPACE_FULL, upk);
+    Mac[k] = gc.rho * moment(gc, SPACE_FULL, mul(upk, transport_c));
+    MAc[k] = gc.rho * moment(gc, SPACE_FULL, mul(upk, Apc));
+    Flr[k] = gl.rho * moment(gl, SPACE_POS, upk) + gr.rho * moment(gr, SPACE_NEG, upk);
+    Malr[k] = gl.rho * moment(gl, SPACE_POS, mul(upk, transport_l)) +
+              gr.rho * moment(gr, SPACE_NEG, mul(upk, transport_r));
+  }
+  /* Section 2.2: numerical collision time. */
+  T pl = pressure(Wl, gamma), pr = pressure(Wr, gamma);
+  T tau = C1 * dt + C2 * mabs((pl - pr) / (pl + pr)) * dt;
+  /* eq. (25): time integral of the flux over [0, delta]:
+   *   int (1 - E) dt = delta - tau (1 - e),  int t E dt = tau^2 (1 - e) - tau delta e,
+   *   int t dt = delta^2 / 2,                int E dt = tau (1 - e),   e = exp(-delta / tau). */
+  auto integral = [&](double delta, T* out) {
+    T q1, q2, q4;
+    if (val(tau) == 0.0) {
+      q1 = T(delta);
+      q2 = T(0.0);
+      q4 = T(0.0);
+    } else {
+      T e = mexp(-(delta / tau));
+      q1 = delta - tau * (1.0 - e);
+      q2 = tau * tau * (1.0 - e) - tau * delta * e;
+      q4 = tau * (1.0 - e);
+    }
+    double q3 = 0.5 * delta * delta;
+    for (int k = 0; k < 4; ++k) out[k] = q1 * Fc[k] + q2 * Mac[k] + q3 * MAc[k] + q4 * Flr[k] - q2 * Malr[k];
+  };
+  T Ffull[4], Fhalf[4];
+  integral(dt, Ffull);
+  integral(0.5 * dt, Fhalf);
+  /* eq. (26) fitted to F(dt) and F(dt/2): F^n dt + F_t dt^2/2 = F(dt), F^n dt/2 + F_t dt^2/8 = F(dt/2). */
+  for (int k = 0; k < 4; ++k) {
+    F[k] = (4.0 * Fhalf[k] - Ffull[k]) / dt;
+    Ft[k] = 4.0 * (Ffull[k] - 2.0 * Fhalf[k]) / (dt * dt);
+  }
+}
+
+/* Section 3.2: DF at one Gauss point from the left/right states in the local frame. */
+template <class T>
+static T df_gauss_point(const T* Wl, const T* Wr, double gamma) {
+  T pl = pressure(Wl, gamma), pr = pressure(Wr, gamma);
+  T cl = msqrt(gamma * pl / Wl[0]), cr = msqrt(gamma * pr / Wr[0]);
+  T Mnl = (Wl[1] / Wl[0]) / cl, Mnr = (Wr[1] / Wr[0]) / cr;
+  T Mtl = (Wl[2] / Wl[0]) / cl, Mtr = (Wr[2] / Wr[0]) / cr;
+  T jump = mabs(pl - pr);
+  T D = jump / pl + jump / pr + sq(Mnl - Mnr) + sq(Mtl - Mtr);
+  return 1.0 / (1.0 + D * D);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Ghost arrays (Algorithm 1: "update boundary condition"); widths 3 (W) and 2 (alpha).        */
+/* ------------------------------------------------------------------------------------------ */
+constexpr int GW = 3, GA = 2;
+
+static int bc_index(int i, int n, int bc) {
+  if (bc == BC_PERIODIC) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <class T>
+struct Ghosted {
+  int nx, ny, g;
+  std::vector<T> a;
+  int comps;
+  T& at(int c, int i, int j) { return a[((size_t)c * (ny + 2 * g) + (j + g)) * (nx + 2 * g) + (i + g)]; }
+  const T& at(int c, int i, int j) const { return a[((size_t)c * (ny + 2 * g) + (j + g)) * (nx + 2 * g) + (i + g)]; }
+};
+
+template <class T>
+static Ghosted<T> fill_ghosts(const T* A, int comps, const Grid& G, int g) {
+  Ghosted<T> out;
+  out.nx = G.nx;
+  out.ny = G.ny;
+  out.g = g;
+  out.comps = comps;
+  out.a.assign((size_t)comps * (G.ny + 2 * g) * (G.nx + 2 * g), T(0.0));
+  for (int c = 0; c < comps; ++c)
+    for (int j = -g; j < G.ny + g; ++j)
+      for (int i = -g; i < G.nx + g; ++i) {
+        int si = bc_index(i, G.nx, G.bc_x), sj = bc_index(j, G.ny, G.bc_y);
+        out.at(c, i, j) = A[((size_t)c * G.ny + sj) * G.nx + si];
+      }
+  return out;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* The spatial operator of one stage: L(W), d/dt L(W), and the per-cell DF product built from */
+/* this stage's Gauss-point states.                                                            */
+/* dir = 0: x-interfaces (normal x, tangential y); dir = 1: y-interfaces.                     */
+/* ------------------------------------------------------------------------------------------ */
+template <class T>
+struct FaceData { /* per interface: face-averaged flux, its time derivative, DF of the 2 GPs */
+  std::vector<T> F, Ft, a1, a2;
+};
+
+template <class T>
+static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Grid& G,
+                  const Params& prm, double dt, FaceData<T>& out) {
+  const Frame fr = kFrame[dir];
+  const double gamma = prm.gamma;
+  const int Nn = dir == 0 ? G.nx : G.ny;   /* cells along the normal */
+  const int Nt = dir == 0 ? G.ny : G.nx;   /* cells along the tangential direction */
+  const double dn = dir == 0 ? G.dx : G.dy, dtan = dir == 0 ? G.dy : G.dx;
+  const double tsign = dir == 0 ? 1.0 : -1.0; /* local tangential axis vs the global one */
+  auto W = [&](int n, int t, T* w) {
+    for (int c = 0; c < 4; ++c) w[c] = dir == 0 ? Wg.at(c, n, t) : Wg.at(c, t, n);
+  };
+  auto A = [&](int n, int t) -> T { return dir == 0 ? Ag.at(0, n, t) : Ag.at(0, t, n); };
+  const int NF = Nn + 1; /* interface f lies between cells f-1 and f */
+  const int TR0 = -2, TR = Nt + 4;
+  /* normal sweep: line values (left/right) and their normal derivatives, rows -2..Nt+1 */
+  std::vector<T> lineL((size_t)TR * NF * 4), lineR((size_t)TR * NF * 4), lineLn((size_t)TR * NF * 4),
+      lineRn((size_t)TR * NF * 4);
+#pragma omp parallel for schedule(static)
+  for (int rt = 0; rt < TR; ++rt) {
+    int t = rt + TR0;
+    for (int f = 0; f < NF; ++f) {
+      T w0[4], w1[4], wm[4], R[16], L[16];
+      W(f - 1, t, w0);
+      W(f, t, w1);
+      for (int c = 0; c < 4; ++c) wm[c] = 0.5 * (w0[c] + w1[c]);
+      char_basis(fr, wm, gamma, R, L);
+      T Q[6][4];
+      for (int k = 0; k < 6; ++k) {
+        T w[4];
+        W(f - 3 + k, t, w);
+        matvec4(L, w, Q[k]);
+      }
+      T al[3] = {A(f - 2, t), A(f - 1, t), A(f, t)};
+      T ar[3] = {A(f - 1, t), A(f, t), A(f + 1, t)};
+      T ql[4], qln[4], qr[4], qrn[4];
+      for (int c = 0; c < 4; ++c) {
+        T s[5], P[5];
+        for (int m = 0; m < 5; ++m) s[m] = Q[m][c]; /* cell f-1 and its stencil f-3..f+1 */
+        hybrid_poly(s, al, prm, P);
+        ql[c] = poly_eval(P, 4, 0.0);                 /* right edge of cell f-1 */
+        qln[c] = poly_deriv_eval(P, 4, 0.0) / dn;
+        for (int m = 0; m < 5; ++m) s[m] = Q[m + 1][c]; /* cell f and its stencil f-2..f+2 */
+        hybrid_poly(s, ar, prm, P);
+        qr[c] = poly_eval(P, 4, -1.0);                /* left edge of cell f */
+        qrn[c] = poly_deriv_eval(P, 4, -1.0) / dn;
+      }
+      size_t o = ((size_t)rt * NF + f) * 4;
+      matvec4(R, ql, &lineL[o]);
+      matvec4(R, qln, &lineLn[o]);
+      matvec4(R, qr, &lineR[o]);
+      matvec4(R, qrn, &lineRn[o]);
+    }
+  }
+  /* tangential sweep at the Gauss points, fluxes, DF per Gauss point */
+  out.F.assign((size_t)Nt * NF * 4, T(0.0));
+  out.Ft.assign((size_t)Nt * NF * 4, T(0.0));
+  out.a1.assign((size_t)Nt * NF, T(0.0));
+  out.a2.assign((size_t)Nt * NF, T(0.0));
+  const double xi_gp[2] = {-0.5 - std::sqrt(3.0) / 6.0, -0.5 + std::sqrt(3.0) / 6.0};
+#pragma omp parallel for schedule(static)
+  for (int t = 0; t < Nt; ++t) {
+    for (int f = 0; f < NF; ++f) {
+      T w0[4], w1[4], wm[4], R[16], L[16];
+      W(f - 1, t, w0);
+      W(f, t, w1);
+      for (int c = 0; c < 4; ++c) wm[c] = 0.5 * (w0[c] + w1[c]);
+      char_basis(fr, wm, gamma, R, L);
+      T gpW[2][2][4], gpWt[2][2][4], gpWn[2][4]; /* [side][gp][comp] */
+      for (int side = 0; side < 2; ++side) {
+        const std::vector<T>& line = side == 0 ? lineL : lineR;
+        const std::vector<T>& linen = side == 0 ? lineLn : lineRn;
+        int cell = side == 0 ? f - 1 : f; /* DF of the cell on the same side as the point */
+        T a3[3] = {A(cell, t - 1), A(cell, t), A(cell, t + 1)};
+        T Q[5][4];
+        for (int k = 0; k < 5; ++k) matvec4(L, &line[((size_t)(t + k - 2 - TR0) * NF + f) * 4], Q[k]);
+        T qv[2][4], qd[2][4];
+        for (int c = 0; c < 4; ++c) {
+          T s[5], P[5];
+          for (int k = 0; k < 5; ++k) s[k] = Q[k][c];
+          hybrid_poly(s, a3, prm, P);
+          for (int m = 0; m < 2; ++m) {
+            qv[m][c] = poly_eval(P, 4, xi_gp[m]);
+            qd[m][c] = poly_deriv_eval(P, 4, xi_gp[m]) / dtan;
+          }
+        }
+        for (int m = 0; m < 2; ++m) {
+          matvec4(R, qv[m], gpW[side][m]);
+          matvec4(R, qd[m], gpWt[side][m]);
+        }
+        for (int c = 0; c < 4; ++c) gpWn[side][c] = linen[((size_t)(t - TR0) * NF + f) * 4 + c];
+      }
+      T Fsum[4], Ftsum[4], agp[2];
+      for (int m = 0; m < 2; ++m) {
+        T lw[2][4], lwn[2][4], lwt[2][4];
+        for (int side = 0; side < 2; ++side) {
+          rotate(fr, gpW[side][m], lw[side]);
+          rotate(fr, gpWn[side], lwn[side]);
+          T tmp[4];
+          rotate(fr, gpWt[side][m], tmp);
+          for (int c = 0; c < 4; ++c) lwt[side][c] = tsign * tmp[c];
+        }
+        T Fl[4], Ftl[4];
+        if (prm.flux == FLUX_LF)
+          lf_flux(lw[0], lwn[0], lwt[0], lw[1], lwn[1], lwt[1], gamma, Fl, Ftl);
+        else
+          gks_flux(lw[0], lwn[0], lwt[0], lw[1], lwn[1], lwt[1], gamma, dt, prm.c1, prm.c2, Fl, Ftl);
+        T Fg[4], Ftg[4];
+        rotate_back(fr, Fl, Fg);
+        rotate_back(fr, Ftl, Ftg);
+        for (int c = 0; c < 4; ++c) { /* Gauss quadrature, A_1 = A_2 = 1/2 */
+          if (m == 0) {
+            Fsum[c] = 0.5 * Fg[c];
+            Ftsum[c] = 0.5 * Ftg[c];
+          } else {
+            Fsum[c] = Fsum[c] + 0.5 * Fg[c];
+            Ftsum[c] = Ftsum[c] + 0.5 * Ftg[c];
+          }
+        }
+        agp[m] = df_gauss_point(lw[0], lw[1], gamma);
+      }
+      size_t o = (size_t)t * NF + f;
+      for (int c = 0; c < 4; ++c) {
+        out.F[o * 4 + c] = Fsum[c];
+        out.Ft[o * 4 + c] = Ftsum[c];
+      }
+      out.a1[o] = agp[0];
+      out.a2[o] = agp[1];
+    }
+  }
+}
+
+/* eq. (2) with the Gauss quadrature: L = -(1/|Omega|) sum_p |l_p| sum_m A_m F(x_pm) . n_p. */
+template <class T>
+static void spatial_operator(const T* Win, const T* alpha, const Grid& G, const Params& prm,
+                             double dt, T* Lout, T* Ltout, T* alpha_new) {
+  Ghosted<T> Wg = fill_ghosts(Win, 4, G, GW);
+  Ghosted<T> Ag = fill_ghosts(alpha, 1, G, GA);
+  FaceData<T> X, Y;
+  sweep(0, Wg, Ag, G, prm, dt, X);
+  sweep(1, Wg, Ag, G, prm, dt, Y);
+  const int nx = G.nx, ny = G.ny;
+  const double area = G.dx * G.dy;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      size_t west = (size_t)j * (nx + 1) + i, east = west + 1;
+      size_t south = (size_t)i * (ny + 1) + j, north = south + 1;
+      for (int c = 0; c < 4; ++c) {
+        /* outward normals: east +x, west -x, north +y, south -y */
+        T s = G.dy * X.F[east * 4 + c] - G.dy * X.F[west * 4 + c] + G.dx * Y.F[north * 4 + c] -
+              G.dx * Y.F[south * 4 + c];
+        T st = G.dy * X.Ft[east * 4 + c] - G.dy * X.Ft[west * 4 + c] + G.dx * Y.Ft[north * 4 + c] -
+               G.dx * Y.Ft[south * 4 + c];
+        size_t o = ((size_t)c * ny + j) * nx + i;
+        Lout[o] = -(s / area);
+        Ltout[o] = -(st / area);
+      }
+      if (alpha_new) { /* Section 3.2: product over the 4 interfaces and their 2 Gauss points */
+        T a = X.a1[west] * X.a2[west];
+        a = a * X.a1[east];
+        a = a * X.a2[east];
+        a = a * Y.a1[south];
+        a = a * Y.a2[south];
+        a = a * Y.a1[north];
+        a = a * Y.a2[north];
+        alpha_new[(size_t)j * nx + i] = a;
+      }
+    }
+}
+
+/* (R3) largest signal speed over dx; returns false on a non-physical or non-finite state. */
+static bool max_speed(const double* W, const Grid& G, double gamma, double* smax) {
+  const size_t N = (size_t)G.nx * G.ny;
+  double m = 0.0;
+  bool ok = true;
+  for (size_t k = 0; k < N; ++k) {
+    double w[4] = {W[k], W[N + k], W[2 * N + k], W[3 * N + k]};
+    double p = pressure(w, gamma);
+    if (!(w[0] > 0.0) || !(p > 0.0) || !std::isfinite(w[1]) || !std::isfinite(w[2]) || !std::isfinite(w[3]) ||
+        !std::isfinite(p)) {
+      ok = false;
+      continue;
+    }
+    double c = std::sqrt(gamma * p / w[0]);
+    double sx = (std::fabs(w[1] / w[0]) + c) / G.dx;
+    double sy = (std::fabs(w[2] / w[0]) + c) / G.dy;
+    m = std::max(m, std::max(sx, sy));
+  }
+  *smax = m;
+  return ok;
+}
+
+/* Eq. (24), S2O4:  W* = W^n + dt/2 L^n + dt^2/8 L_t^n,
+ *                  W^{n+1} = W^n + dt L^n + dt^2/6 (L_t^n + 2 L_t^*).
+ * op(W, L, Lt, stage) evaluates the operator and its time derivative; only L_t of the second
+ * stage enters the update. */
+template <class T, class Op>
+static void s2o4(T* W, size_t n, double dt, Op op) {
+  std::vector<T> L0(n), Lt0(n), Ws(n), L1(n), Lt1(n);
+  op(W, L0.data(), Lt0.data(), 0);
+  for (size_t k = 0; k < n; ++k) Ws[k] = W[k] + 0.5 * dt * L0[k] + (dt * dt / 8.0) * Lt0[k];
+  op(Ws.data(), L1.data(), Lt1.data(), 1);
+  for (size_t k = 0; k < n; ++k) W[k] = W[k] + dt * L0[k] + (dt * dt / 6.0) * (Lt0[k] + 2.0 * Lt1[k]);
+}
+
+template <class T>
+static void s2o4_step(T* W, T* alpha, const Grid& G, const Params& prm, double dt) {
+  const size_t N = (size_t)G.nx * G.ny;
+  std::vector<T> an(N);
+  s2o4(W, 4 * N, dt, [&](const T* w, T* L, T* Lt, int stage) {
+    /* alpha^n in both stages (R6); alpha^{n+1} from the second stage's Gauss points (R5) */
+    spatial_operator(w, alpha, G, prm, dt, L, Lt, stage == 1 ? an.data() : (T*)nullptr);
+  });
+  for (size_t k = 0; k < N; ++k) alpha[k] = an[k];
+}
+
+}  // namespace dfo
+
+/* ============================================================================================ */
+/* C ABI for the Python test harness.                                                           */
+/* ============================================================================================ */
+using namespace dfo;
+
+extern "C" {
+
+struct dfo_grid {
+  int32_t nx, ny;
+  double dx, dy;
+  int32_t bc_x, bc_y;
+};
+struct dfo_params {
+  double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
+  int32_t flux;
+};
+
+static Grid to_grid(const dfo_grid* g) { return Grid{g->nx, g->ny, g->dx, g->dy, g->bc_x, g->bc_y}; }
+static Params to_params(const dfo_params* p) {
+  return Params{p->gamma, p->cfl, p->dt_fixed, p->alpha_thres, p->d_h, p->d_l, p->eps_weno, p->c1, p->c2, p->flux};
+}
+
+/* 0 on success, 1 when the state holds a non-positive density/pressure or a non-finite value. */
+int dfo_max_speed(const double* W, const dfo_grid* g, const dfo_params* p, double* smax) {
+  return max_speed(W, to_grid(g), p->gamma, smax) ? 0 : 1;
+}
+
+/* Spatial operator of one stage (L, dL/dt) and, if alpha_new is non-null, the DF product of
+ * every cell built from this stage's Gauss-point states.  dt enters only the GKS flux. */
+void dfo_rhs(const double* W, const double* alpha, const dfo_grid* g, const dfo_params* p, double dt,
+             double* L, double* Lt, double* alpha_new) {
+  spatial_operator(W, alpha, to_grid(g), to_params(p), dt, L, Lt, alpha_new);
+}
+
+/* nsteps S2O4 steps in place.  dt from the CFL condition unless dt_fixed > 0.  Returns 0, or 1
+ * with *fail_step = the number of completed steps when a non-physical state is met. */
+int dfo_run(double* W, double* alpha, const dfo_grid* g, const dfo_params* p, int32_t nsteps,
+            double* dt_hist, double* t_out, int32_t* fail_step) {
+  Grid G = to_grid(g);
+  Params P = to_params(p);
+  double t = 0.0;
+  if (fail_step) *fail_step = -1;
+  for (int n = 0; n < nsteps; ++n) {
+    double smax;
+    bool ok = max_speed(W, G, P.gamma, &smax);
+    if (!ok) {
+      if (fail_step) *fail_step = n;
+      if (t_out) *t_out = t;
+      return 1;
+    }
+    double dt = P.dt_fixed > 0.0 ? P.dt_fixed : P.cfl / smax;
+    s2o4_step(W, alpha, G, P, dt);
+    if (dt_hist) dt_hist[n] = dt;
+    t += dt;
+  }
+  {
+    double smax;
+    if (!max_speed(W, G, P.gamma, &smax)) {
+      if (fail_step) *fail_step = nsteps;
+      if (t_out) *t_out = t;
+      return 1;
+    }
+  }
+  if (t_out) *t_out = t;
+  return 0;
+}
+
+/* Forward-mode tangent of nsteps steps with the time steps frozen to dt_hist:
+ * (W, alpha) advance as in dfo_run and (dW, dalpha) carry the directional derivative. */
+void dfo_run_tangent(double* W, double* alpha, double* dW, double* dalpha, const dfo_grid* g,
+                     const dfo_params* p, int32_t nsteps, const double* dt_hist) {
+  Grid G = to_grid(g);
+  Params P = to_params(p);
+  const size_t N = (size_t)G.nx * G.ny;
+  std::vector<Dual<double>> w(4 * N), a(N);
+  for (size_t k = 0; k < 4 * N; ++k) w[k] = Dual<double>(W[k], dW[k]);
+  for (size_t k = 0; k < N; ++k) a[k] = Dual<double>(alpha[k], dalpha[k]);
+  for (int n = 0; n < nsteps; ++n) s2o4_step(w.data(), a.data(), G, P, dt_hist[n]);
+  for (size_t k = 0; k < 4 * N; ++k) {
+    W[k] = w[k].v;
+    dW[k] = w[k].d;
+  }
+  for (size_t k = 0; k < N; ++k) {
+    alpha[k] = a[k].v;
+    dalpha[k] = a[k].d;
+  }
+}
+
+/* ---- unit-level entry points (pins) ---- */
+
+/* coef[n*5 + m]: coefficient of xi^n in candidate p_k for the average Q_{i-2+m}. */
+void dfo_candidate(int32_t k, double* coef) {
+  const Candidates& C = candidates();
+  for (int n = 0; n < 5; ++n)
+    for (int m = 0; m < 5; ++m) coef[n * 5 + m] = C.coef[k][n][m];
+}
+
+double dfo_smoothness(const double* coef, int32_t deg) { return smoothness(coef, deg); }
+
+void dfo_weno_ao(const double* Q, const dfo_params* p, double* P) { weno_ao_poly(Q, to_params(p), P); }
+
+void dfo_hybrid(const double* Q, const double* a3, const dfo_params* p, double* P) {
+  hybrid_poly(Q, a3, to_params(p), P);
+}
+
+void dfo_char_basis(int32_t dir, const double* W, double gamma, double* R, double* L) {
+  char_basis(kFrame[dir], W, gamma, R, L);
+}
+
+/* Local-frame flux at one Gauss point: flux 0 = LF, 1 = GKS. */
+void dfo_flux_gp(int32_t flux, const double* Wl, const double* Wlx, const double* Wly, const double* Wr,
+                 const double* Wrx, const double* Wry, double gamma, double dt, double c1, double c2,
+                 double* F, double* Ft) {
+  if (flux == FLUX_LF) lf_flux(Wl, Wlx, Wly, Wr, Wrx, Wry, gamma, F, Ft);
+  else gks_flux(Wl, Wlx, Wly, Wr, Wrx, Wry, gamma, dt, c1, c2, F, Ft);
+}
+
+/* One S2O4 step of the scalar ODE u' = lam u with the exact operator derivative lam^2 u. */
+double dfo_s2o4_scalar(double u, double lam, double dt) {
+  s2o4(&u, 1, dt, [&](const double* w, double* L, double* Lt, int) {
+    L[0] = lam * w[0];
+    Lt[0] = lam * lam * w[0];
+  });
+  return u;
+}
+
+double dfo_df_gp(const double* Wl, const double* Wr, double gamma) { return df_gauss_point(Wl, Wr, gamma); }
+
+/* u-moments 0..n-1 of the normalised Maxwellian (space 0 full, 1 u>0, 2 u<0). */
+void dfo_u_moments(double U, double lam, int32_t space, int32_t n, double* M) {
+  double m[kMaxU + 1];
+  u_moments(U, lam, space, m);
+  for (int i = 0; i < n && i <= kMaxU; ++i) M[i] = m[i];
+}
+
+void dfo_micro_slope(const double* W, const double* dW, double gamma, double* a) {
+  Maxwellian<double> g = maxwellian(W, gamma);
+  micro_slope(g, dW, a);
+}
+
+/* Moment rho <u^a v^b xi^{2c}> under the Maxwellian of W, in the given space. */
+double dfo_moment(const double* W, double gamma, int32_t space, int32_t a, int32_t b, int32_t c) {
+  Maxwellian<double> g = maxwellian(W, gamma);
+  KPoly<double> P;
+  P.add(a, b, c, 1.0);
+  return g.rho * moment(g, space, P);
+}
+
+}  /* extern "C" */
