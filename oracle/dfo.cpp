@@ -75,6 +75,7 @@ template <class T> Dual<T>& operator-=(Dual<T>& a, const Dual<T>& b) { a = a - b
 template <class T> Dual<T>& operator*=(Dual<T>& a, const Dual<T>& b) { a = a * b; return a; }
 
 inline double msqrt(double x) { return std::sqrt(x); }
+inline long double mexp(long double x) { return std::exp(x); }
 inline double mexp(double x) { return std::exp(x); }
 inline double merfc(double x) { return std::erfc(x); }
 template <class T> Dual<T> msqrt(const Dual<T>& a) { T s = msqrt(a.v); return Dual<T>(s, a.d / (2.0 * s)); }
@@ -93,6 +94,10 @@ template <class T> T mabs(const T& a) {
 /* max(a, b) routes to a when a >= b. */
 template <class T> T mmax(const T& a, const T& b) { return val(a) >= val(b) ? a : b; }
 template <class T> T sq(const T& a) { return a * a; }
+
+/* Extended-precision companion type used where a formula of the paper cancels catastrophically. */
+template <class T> struct Wide { using type = T; };
+template <> struct Wide<double> { using type = long double; };
 
 /* ------------------------------------------------------------------------------------------ */
 /* Problem description.                                                                        */
@@ -600,29 +605,37 @@ static void gks_flux(const T* Wl, const T* Wlx, const T* Wly, const T* Wr, const
   T tau = C1 * dt + C2 * mabs((pl - pr) / (pl + pr)) * dt;
   /* eq. (25): time integral of the flux over [0, delta]:
    *   int (1 - E) dt = delta - tau (1 - e),  int t E dt = tau^2 (1 - e) - tau delta e,
-   *   int t dt = delta^2 / 2,                int E dt = tau (1 - e),   e = exp(-delta / tau). */
-  auto integral = [&](double delta, T* out) {
-    T q1, q2, q4;
+   *   int t dt = delta^2 / 2,                int E dt = tau (1 - e),   e = exp(-delta / tau).
+   * The fit of eq. (26) below subtracts F(dt) - 2 F(dt/2), which cancels all but an O(dt^2)
+   * part; for plain doubles the integrals and the fit are therefore evaluated in extended
+   * precision (long double) so that the cancellation stays far below FP64 parity tolerances. */
+  using WT = typename Wide<T>::type;
+  const WT tw = WT(tau);
+  auto integral = [&](double delta, WT* out) {
+    WT q1, q2, q4;
+    const WT dl = WT(delta);
     if (val(tau) == 0.0) {
-      q1 = T(delta);
-      q2 = T(0.0);
-      q4 = T(0.0);
+      q1 = dl;
+      q2 = WT(0.0);
+      q4 = WT(0.0);
     } else {
-      T e = mexp(-(delta / tau));
-      q1 = delta - tau * (1.0 - e);
-      q2 = tau * tau * (1.0 - e) - tau * delta * e;
-      q4 = tau * (1.0 - e);
+      WT e = mexp(-(dl / tw));
+      q1 = dl - tw * (WT(1.0) - e);
+      q2 = tw * tw * (WT(1.0) - e) - tw * dl * e;
+      q4 = tw * (WT(1.0) - e);
     }
-    double q3 = 0.5 * delta * delta;
-    for (int k = 0; k < 4; ++k) out[k] = q1 * Fc[k] + q2 * Mac[k] + q3 * MAc[k] + q4 * Flr[k] - q2 * Malr[k];
+    WT q3 = WT(0.5) * dl * dl;
+    for (int k = 0; k < 4; ++k)
+      out[k] = q1 * WT(Fc[k]) + q2 * WT(Mac[k]) + q3 * WT(MAc[k]) + q4 * WT(Flr[k]) - q2 * WT(Malr[k]);
   };
-  T Ffull[4], Fhalf[4];
+  WT Ffull[4], Fhalf[4];
   integral(dt, Ffull);
   integral(0.5 * dt, Fhalf);
   /* eq. (26) fitted to F(dt) and F(dt/2): F^n dt + F_t dt^2/2 = F(dt), F^n dt/2 + F_t dt^2/8 = F(dt/2). */
+  const WT dtw = WT(dt);
   for (int k = 0; k < 4; ++k) {
-    F[k] = (4.0 * Fhalf[k] - Ffull[k]) / dt;
-    Ft[k] = 4.0 * (Ffull[k] - 2.0 * Fhalf[k]) / (dt * dt);
+    F[k] = T((WT(4.0) * Fhalf[k] - Ffull[k]) / dtw);
+    Ft[k] = T(WT(4.0) * (Ffull[k] - WT(2.0) * Fhalf[k]) / (dtw * dtw));
   }
 }
 
