@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the S2O4 DF-hybrid step (Zhang, Ji & Xu, arXiv:2402.10914) on one MI355X.
+
+Default workload: 2-D Euler, FP64, 512 x 512 cells on [0,1]^2, transmissive boundaries, seeded
+four-quadrant Riemann data (seed 2402), gas-kinetic flux, WENO-AO + DF, S2O4, CFL 0.4; one "step"
+is one S2O4 time step of the whole grid (all parts of the path: CFL reduction, ghost fill, DF,
+reconstruction, fluxes with time derivatives, two-stage update).  The timed region runs exactly
+--steps steps from the initial condition after --warmup untimed steps; inputs are resident in HBM
+before timing starts.
+
+Prints one JSON line: cell-updates/s, per-kernel roofline of the dominant kernel (FP64 vector ALU
+bound: its algorithmic flops per launch over its mean launch time, measured with HIP events on the
+launch stream) and the CPU oracle timed on a bounded sample on this host.
+
+Other modes:  --mode copy   plain device copy of known size (calibrates rocprofv3 FETCH/WRITE_SIZE).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6   # TFLOP/s, MI355X FP64 vector
+PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X FP32 vector
+PEAK_HBM = 8000.0       # GB/s
+BYTES_PER_CELL_UPDATE = {8: 216, 4: 108}  # algorithmic HBM bytes of one S2O4 step per cell
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dfw_math.hpp", "dfw_step.hip"):
+        with open(os.path.join(ROOT, "paper_2402_10914_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on the current kernels."""
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def workload(name):
+    from paper_2402_10914_amd import workloads as WL
+    if name == "riemann512_gks":
+        return WL.riemann4(512, seed=2402, flux=WL.FLUX_GKS, cfl=0.4, nsteps=200), "f64"
+    if name == "riemann512_lf":
+        return WL.riemann4(512, seed=2402, flux=WL.FLUX_LF, cfl=0.4, nsteps=200), "f64"
+    if name.startswith("circles4096"):
+        flux = WL.FLUX_GKS if "gks" in name else WL.FLUX_LF
+        return WL.circles(4096, seed=10914, flux=flux, cfl=0.4, nsteps=50), ("f32" if name.endswith("f32") else "f64")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(prob, steps):
+    """The oracle as it stands on this host: `steps` steps of the same grid."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    g = O.make_grid(prob.nx, prob.ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y)
+    p = O.make_params(flux=prob.flux, cfl=prob.cfl)
+    t0 = time.perf_counter()
+    O.run(prob.W, prob.alpha, g, p, steps)
+    el = time.perf_counter() - t0
+    return {"value": prob.nx * prob.ny * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} S2O4 steps of the same {prob.nx}x{prob.ny} grid from the same initial state "
+                      f"({el:.1f} s, OpenMP over rows)"}
+
+
+def copy_mode(args):
+    import torch
+    n = 1 << 26  # 64 Mi doubles = 512 MiB each way
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n,
+                      "launches": args.steps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="riemann512_gks")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--mode", default="step", choices=["step", "copy"])
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (the step is benchmarked on one MI355X); "
+              f"--gpus {args.gpus} / WORLD_SIZE {world} is not supported.", file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "copy":
+        return copy_mode(args)
+
+    import torch
+    from paper_2402_10914_amd import api, flops
+
+    prob, dt_name = workload(args.workload)
+    dtype = torch.float64 if dt_name == "f64" else torch.float32
+    esize = 8 if dtype == torch.float64 else 4
+    params = api.Params(flux=prob.flux, cfl=prob.cfl)
+    st = api.Stepper.for_problem(prob, params, dtype)
+    W0 = torch.tensor(prob.W, dtype=dtype, device="cuda")
+    A0 = torch.tensor(prob.alpha, dtype=dtype, device="cuda")
+    W = W0.clone()
+    A = A0.clone()
+    print(f"# workload {args.workload}: {prob.nx}x{prob.ny} {dt_name} flux={prob.flux} "
+          f"warmup {args.warmup} steps {args.steps}", file=sys.stderr, flush=True)
+
+    if args.warmup > 0:
+        st.run(W, A, args.warmup)
+    W.copy_(W0)
+    A.copy_(A0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_sim, fail = st.run(W, A, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if fail != -1:
+        print(f"# non-physical state after {fail} steps", file=sys.stderr)
+    cells = prob.nx * prob.ny
+    value = cells * args.steps / elapsed
+    print(f"# timed {args.steps} steps in {elapsed * 1e3:.2f} ms -> {value:.4e} cell-updates/s (t_sim {t_sim:.5f})",
+          file=sys.stderr, flush=True)
+
+    roofline = None
+    kernels = None
+    if not args.no_profile:
+        W.copy_(W0)
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        with api.KernelProfile() as kp:
+            st.run(W, A, args.steps)
+        prof = kp.result()
+        kernels = {k: {"avg_us": 1e3 * ms / n if n else None, "launches": n, "total_ms": ms}
+                   for k, (ms, n) in prof.items()}
+        ms1, n1 = prof["faces1"]
+        avg_s = ms1 / n1 / 1e3
+        faces = (prob.nx + 1) * prob.ny + prob.nx * (prob.ny + 1)
+        fl = faces * flops.per_interface(prob.flux, 1)
+        achieved = fl / avg_s / 1e12
+        peak = PEAK_FP64_VALU if esize == 8 else PEAK_FP32_VALU
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4),
+                    "traffic": load_traffic(f"traffic_faces1_{args.workload}.json"),
+                    "kernel": "k_faces (first stage)", "flops_per_launch": fl, "avg_launch_us": round(avg_s * 1e6, 2)}
+        print(f"# faces1 avg {avg_s * 1e6:.1f} us -> {achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
+
+    hbm = BYTES_PER_CELL_UPDATE[esize] * value / 1e9
+    out = {
+        "metric": "cell-updates/s per S2O4 step",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt_name,
+        "data": "synthetic",
+        "config": {"workload": f"{prob.nx}x{prob.ny} four-quadrant Riemann, GKS, WENO-AO+DF, S2O4, CFL 0.4, "
+                               "transmissive" if prob.name == "riemann4" else f"{prob.nx}x{prob.ny} {prob.name}",
+                   "name": args.workload, "nx": prob.nx, "ny": prob.ny, "flux": "gks" if prob.flux else "lf",
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "hbm_algorithmic": {"bytes_per_cell_update": BYTES_PER_CELL_UPDATE[esize], "achieved_GBps": round(hbm, 1),
+                            "peak_GBps": PEAK_HBM, "frac": round(hbm / PEAK_HBM, 4)},
+        "flops_per_cell_update": flops.per_cell_update(prob.flux),
+        "kernels": kernels,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,122 @@
+/*
+ * dfweno.h — C ABI of the MI355X (gfx950) implementation of one two-stage fourth-order (S2O4)
+ * time step of the 2-D Euler finite-volume scheme with the hybrid discontinuity-feedback (DF) /
+ * WENO-AO reconstruction of Zhang, Ji & Xu, "A robustness-enhanced reconstruction based on
+ * discontinuity feedback factor for high-order finite volume scheme" (arXiv:2402.10914).
+ *
+ * Problem statement (Algorithm 1 of the paper): input the cell averages W^n and the DF field
+ * alpha^n, output W^{n+1} and alpha^{n+1}; the time increment comes from the CFL condition.
+ *
+ * Conventions shared by every entry point
+ *   - Array pointers marked "device" point to device memory owned by the caller; the library
+ *     never allocates, frees or retains them beyond the call.  Host pointers are marked "host".
+ *   - W is [4][ny][nx] contiguous, component-major: rho, rho*U, rho*V, rho*E (cell averages).
+ *     alpha is [ny][nx] contiguous.  Both have the element type given by `dtype` (DFW_F64 or
+ *     DFW_F32); cell (i, j) is at offset j*nx + i.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.  Work is
+ *     enqueued in stream order; calls that return host values synchronise that stream once.
+ *   - `ws` is a device workspace of at least dfw_workspace_bytes() bytes, 256-byte aligned.
+ *   - Every call returns a dfw_status; on a non-OK status dfw_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ */
+#ifndef DFWENO_H
+#define DFWENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DFW_OK = 0,
+  DFW_EINVAL = 1,      /* invalid argument (null pointer, size, unknown flux/bc/dtype, gamma <= 1, ...) */
+  DFW_EDTYPE = 2,      /* unsupported element type */
+  DFW_EWORKSPACE = 3,  /* workspace missing, misaligned or too small */
+  DFW_EHIP = 4,        /* a HIP runtime call failed */
+  DFW_ENONPHYS = 5     /* a state with rho <= 0, p <= 0 or a non-finite value was met */
+} dfw_status;
+
+enum { DFW_FLUX_LF = 0, DFW_FLUX_GKS = 1 };        /* Section 2.3 (Lax-Friedrichs), Section 2.2 (gas-kinetic) */
+enum { DFW_BC_PERIODIC = 0, DFW_BC_TRANSMISSIVE = 1 };
+enum { DFW_F64 = 0, DFW_F32 = 1 };
+
+/* Uniform structured grid: nx by ny cells of size dx by dy; one boundary type per axis.
+ * Transmissive = ghost cells copy the nearest interior cell ("free" boundary of the paper). */
+typedef struct {
+  int32_t nx, ny;
+  double dx, dy;
+  int32_t bc_x, bc_y;
+} dfw_grid;
+
+/* Scheme parameters (defaults of the paper in brackets).
+ *   gamma        ratio of specific heats [1.4]
+ *   cfl          dt = cfl / max over cells of max((|U|+c)/dx, (|V|+c)/dy)   [0.5]
+ *   dt_fixed     if > 0, every step uses this dt instead of the CFL condition
+ *   alpha_thres  DF threshold of the hybrid switch, eq. (34), strict "<" [0.5]
+ *   d_h, d_l     linear-weight parameters of WENO-AO (Section 3.1) [0.85, 0.85]
+ *   eps_weno     epsilon of the WENO-Z weights (not given by the paper) [1e-6]
+ *   c1, c2       numerical collision time tau_n = c1 dt + c2 |(pl-pr)/(pl+pr)| dt (Section 2.2) [0.01, 5]
+ *   flux         DFW_FLUX_LF or DFW_FLUX_GKS */
+typedef struct {
+  double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
+  int32_t flux;
+  int32_t reserved; /* must be 0 */
+} dfw_params;
+
+/* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */
+size_t dfw_workspace_bytes(const dfw_grid* grid, int32_t dtype);
+
+/* Advance (W, alpha) in place by nsteps S2O4 steps (eq. (24); Algorithm 1).
+ *   W, alpha        device, in/out.
+ *   dt_hist_dev     device, optional (may be NULL): receives the nsteps time increments (FP64).
+ *   t_out           host, optional: sum of the time increments actually taken.
+ *   fail_step       host, optional: -1 on success; otherwise the number of completed steps when
+ *                   a non-physical state was found (0 = the input).  W then holds that state and
+ *                   later steps are skipped; the call returns DFW_ENONPHYS.
+ * Synchronises `stream` once at the end. */
+dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
+                   int32_t dtype, void* ws, size_t ws_bytes, double* dt_hist_dev, double* t_out,
+                   int32_t* fail_step, void* stream);
+
+/* The CFL reduction alone: smax = max over cells of max((|U|+c)/dx, (|V|+c)/dy).
+ *   W device in; smax (host, FP64) and nonphys (host, 0/1) out.  Synchronises `stream`. */
+dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* params, int32_t dtype,
+                         void* ws, size_t ws_bytes, double* smax, int32_t* nonphys, void* stream);
+
+/* The spatial operator of one stage, eq. (2) with its time derivative (Section 2.2): for the
+ * state W and DF field alpha, writes L(W) and dL/dt(W) ([4][ny][nx], device) and, if alpha_new
+ * is non-NULL, the DF product of every cell built from this stage's Gauss-point states
+ * ([ny][nx], device).  dt is used only by the gas-kinetic flux.  Stream-ordered, no sync. */
+dfw_status dfw_rhs(const void* W, const void* alpha, const dfw_grid* grid, const dfw_params* params,
+                   int32_t dtype, double dt, void* L, void* Lt, void* alpha_new, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* Measurement support: per-kernel device time of the launches made by dfw_run, recorded with HIP
+ * events on the stream the kernels run on.  Kernel kinds index the arrays of dfw_profile_read. */
+enum {
+  DFW_K_FACES1 = 0,   /* interface kernel, first stage (flux and time derivative) */
+  DFW_K_UPDATE1 = 1,  /* cell kernel, first stage (W*, and the S2O4 accumulator) */
+  DFW_K_FACES2 = 2,   /* interface kernel, second stage (time derivative and DF) */
+  DFW_K_UPDATE2 = 3,  /* cell kernel, second stage (W^{n+1}, alpha^{n+1}, CFL reduction) */
+  DFW_K_SPEED = 4,    /* standalone CFL reduction of the input state */
+  DFW_K_COUNT = 5
+};
+
+/* enable != 0 clears the records and starts recording; 0 stops.  Process-wide, not thread-safe;
+ * meant for benchmarks only (recording adds two events per launch). */
+dfw_status dfw_profile(int32_t enable);
+
+/* Synchronises the recorded events and writes, for each kind k < n, the summed device time in
+ * milliseconds (ms[k], host) and the number of launches (launches[k], host). */
+dfw_status dfw_profile_read(double* ms, int64_t* launches, int32_t n);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* dfw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFWENO_H */

@@ -1,0 +1,162 @@
+"""PyTorch-facing API of the S2O4 DF-hybrid step (Zhang, Ji & Xu, arXiv:2402.10914).
+
+PyTorch supplies device memory and the current stream; every step of the method runs in the HIP
+kernels of ``libdfweno.so`` through the C ABI of ``include/dfweno.h``.
+
+    st = Stepper(nx, ny, dx, dy, bc_x, bc_y, params=Params(flux=FLUX_GKS, cfl=0.4))
+    t, fail_step = st.run(W, alpha, nsteps)     # W [4, ny, nx], alpha [ny, nx], CUDA tensors, in place
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (DFW_BC_PERIODIC, DFW_BC_TRANSMISSIVE, DFW_ENONPHYS, DFW_F32, DFW_F64, DFW_FLUX_GKS,
+                   DFW_FLUX_LF, DFW_OK, DFWError)
+
+FLUX_LF, FLUX_GKS = DFW_FLUX_LF, DFW_FLUX_GKS
+BC_PERIODIC, BC_TRANSMISSIVE = DFW_BC_PERIODIC, DFW_BC_TRANSMISSIVE
+
+
+@dataclass
+class Params:
+    """Scheme parameters; defaults are the paper's (eps_weno is not given by the paper)."""
+    flux: int = FLUX_LF
+    gamma: float = 1.4
+    cfl: float = 0.5
+    dt_fixed: float = 0.0
+    alpha_thres: float = 0.5
+    d_h: float = 0.85
+    d_l: float = 0.85
+    eps_weno: float = 1e-6
+    c1: float = 0.01
+    c2: float = 5.0
+
+    def struct(self) -> _lib.dfw_params:
+        return _lib.dfw_params(float(self.gamma), float(self.cfl), float(self.dt_fixed), float(self.alpha_thres),
+                               float(self.d_h), float(self.d_l), float(self.eps_weno), float(self.c1),
+                               float(self.c2), int(self.flux), 0)
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt == torch.float64:
+        return DFW_F64
+    if dt == torch.float32:
+        return DFW_F32
+    raise TypeError(f"unsupported dtype {dt}; use torch.float64 or torch.float32")
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Stepper:
+    """Owns the device workspace for one grid and element type."""
+
+    def __init__(self, nx: int, ny: int, dx: float, dy: float, bc_x: int = BC_PERIODIC, bc_y: int | None = None,
+                 params: Params | None = None, dtype: torch.dtype = torch.float64, device="cuda"):
+        self.lib = _lib.load()
+        self.grid = _lib.dfw_grid(int(nx), int(ny), float(dx), float(dy), int(bc_x),
+                                  int(bc_x if bc_y is None else bc_y))
+        self.params = params or Params()
+        self.dtype = dtype
+        self.code = _dtype_code(dtype)
+        self.device = torch.device(device)
+        nbytes = self.lib.dfw_workspace_bytes(ctypes.byref(self.grid), self.code)
+        if nbytes == 0:
+            raise DFWError(_lib.DFW_EINVAL, "invalid grid")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+        self.ws_bytes = nbytes
+
+    @classmethod
+    def for_problem(cls, prob, params: Params, dtype=torch.float64, device="cuda"):
+        return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y, params, dtype, device)
+
+    def _check(self, W: torch.Tensor, alpha: torch.Tensor | None = None):
+        g = self.grid
+        if W.shape != (4, g.ny, g.nx) or W.dtype != self.dtype or not W.is_contiguous() or W.device.type != "cuda":
+            raise ValueError(f"W must be a contiguous {self.dtype} CUDA tensor of shape (4, {g.ny}, {g.nx})")
+        if alpha is not None and (alpha.shape != (g.ny, g.nx) or alpha.dtype != self.dtype
+                                  or not alpha.is_contiguous() or alpha.device.type != "cuda"):
+            raise ValueError(f"alpha must be a contiguous {self.dtype} CUDA tensor of shape ({g.ny}, {g.nx})")
+
+    def run(self, W: torch.Tensor, alpha: torch.Tensor, nsteps: int, dt_hist: torch.Tensor | None = None,
+            params: Params | None = None, strict: bool = False):
+        """Advance (W, alpha) in place by nsteps S2O4 steps.  Returns (t, fail_step); fail_step is -1
+        unless a non-physical state was met (then W holds it; strict=True raises instead)."""
+        self._check(W, alpha)
+        if dt_hist is not None and (dt_hist.dtype != torch.float64 or dt_hist.numel() < nsteps
+                                    or not dt_hist.is_contiguous()):
+            raise ValueError("dt_hist must be a contiguous float64 CUDA tensor with >= nsteps entries")
+        p = (params or self.params).struct()
+        t = ctypes.c_double(0.0)
+        fs = ctypes.c_int32(-1)
+        st = self.lib.dfw_run(_ptr(W), _ptr(alpha), ctypes.byref(self.grid), ctypes.byref(p), int(nsteps), self.code,
+                              self.ws_ptr, self.ws_bytes, _ptr(dt_hist) if dt_hist is not None else None,
+                              ctypes.byref(t), ctypes.byref(fs), _stream_ptr(self.device))
+        if st == DFW_ENONPHYS and not strict:
+            return t.value, fs.value
+        _lib.check(st)
+        return t.value, fs.value
+
+    def max_speed(self, W: torch.Tensor):
+        """CFL reduction: (max over cells of max((|U|+c)/dx, (|V|+c)/dy), non-physical flag)."""
+        self._check(W)
+        s = ctypes.c_double(0.0)
+        bad = ctypes.c_int32(0)
+        p = self.params.struct()
+        _lib.check(self.lib.dfw_max_speed(_ptr(W), ctypes.byref(self.grid), ctypes.byref(p), self.code, self.ws_ptr,
+                                          self.ws_bytes, ctypes.byref(s), ctypes.byref(bad),
+                                          _stream_ptr(self.device)))
+        return s.value, bool(bad.value)
+
+    def rhs(self, W: torch.Tensor, alpha: torch.Tensor, dt: float, want_alpha: bool = False):
+        """Spatial operator of one stage: L(W), dL/dt(W) and optionally the DF product per cell."""
+        self._check(W, alpha)
+        L = torch.empty_like(W)
+        Lt = torch.empty_like(W)
+        an = torch.empty_like(alpha) if want_alpha else None
+        p = self.params.struct()
+        _lib.check(self.lib.dfw_rhs(_ptr(W), _ptr(alpha), ctypes.byref(self.grid), ctypes.byref(p), self.code,
+                                    float(dt), _ptr(L), _ptr(Lt), _ptr(an) if an is not None else None,
+                                    self.ws_ptr, self.ws_bytes, _stream_ptr(self.device)))
+        return (L, Lt, an) if want_alpha else (L, Lt)
+
+
+class KernelProfile:
+    """Context manager recording the device time of every kernel launched by Stepper.run (HIP
+    events on the launch stream); .result() -> {kind: (total_ms, launches)}."""
+
+    def __enter__(self):
+        _lib.check(_lib.load().dfw_profile(1))
+        return self
+
+    def __exit__(self, *exc):
+        self._read()
+        _lib.load().dfw_profile(0)
+        return False
+
+    def _read(self):
+        n = len(_lib.KERNEL_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _lib.check(_lib.load().dfw_profile_read(ms, cnt, n))
+        self._res = {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_KINDS)}
+
+    def result(self):
+        return self._res
+
+
+def run(W: torch.Tensor, alpha: torch.Tensor, nx_ny_dx_dy_bc, params: Params, nsteps: int):
+    """One-shot convenience: ((nx, ny, dx, dy, bc_x, bc_y), ...) -> (t, fail_step)."""
+    nx, ny, dx, dy, bcx, bcy = nx_ny_dx_dy_bc
+    return Stepper(nx, ny, dx, dy, bcx, bcy, params, W.dtype, W.device).run(W, alpha, nsteps)

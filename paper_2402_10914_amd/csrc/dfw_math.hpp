@@ -1,0 +1,539 @@
+// Device arithmetic of the S2O4 DF-hybrid step (Zhang, Ji & Xu, arXiv:2402.10914), hand-expanded
+// for gfx950.  Every function works in the local frame of an interface: component 1 is the normal
+// momentum, component 2 the tangential one (y-interfaces swap rho*U and rho*V before calling,
+// an exact reflection of the paper's rotation by pi/2, Section 2.1).
+//
+// Functions are __host__ __device__ so that the same arithmetic can be instantiated on the host
+// with a counting scalar to obtain exact operation counts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define DFW_HD __host__ __device__ __forceinline__
+
+namespace dfw {
+
+// Scheme constants in the working precision, converted once per kernel from the host values.
+template <class real>
+struct Coef {
+  real gamma, gm1, inv_gm1, alpha_thres, eps, c1, c2, K;
+  real d[4];      // WENO-AO linear weights d0..d3 (Section 3.1)
+  real dr[3];     // d_k / d_3
+  real inv_d3;
+};
+
+// ------------------------------------------------------------------------------------------------
+// Characteristic basis (eigenvectors of the normal flux Jacobian at the arithmetic mean of the two
+// cells beside the interface).  Right eigenvectors (columns): (1,u-c,v,H-uc), (1,u,v,q2/2),
+// (0,0,1,v), (1,u+c,v,H+uc).  The left eigenvectors are applied in a factored closed form:
+// with b1 = (gamma-1)/c^2, b2 = b1 q2/2 and T = b2 w0 - b1 (u w1 + v w2 - w3), s = (u w0 - w1)/c:
+//   Q0 = (T + s)/2, Q1 = w0 - T, Q2 = w2 - v w0, Q3 = (T - s)/2.
+// ------------------------------------------------------------------------------------------------
+template <class real>
+struct Basis {
+  real u, v, c, ic, H, hq2, b1, b2;
+};
+
+template <class real>
+DFW_HD Basis<real> make_basis(const real* wa, const real* wb, const Coef<real>& k) {
+  Basis<real> B;
+  const real h = real(0.5);
+  real r = h * (wa[0] + wb[0]);
+  real m = h * (wa[1] + wb[1]);
+  real n = h * (wa[2] + wb[2]);
+  real e = h * (wa[3] + wb[3]);
+  real ir = real(1) / r;
+  B.u = m * ir;
+  B.v = n * ir;
+  B.hq2 = h * (B.u * B.u + B.v * B.v);
+  real p = k.gm1 * (e - r * B.hq2);
+  real c2 = k.gamma * p * ir;
+  B.c = sqrt(c2);
+  B.ic = real(1) / B.c;
+  B.H = (e + p) * ir;
+  B.b1 = k.gm1 / c2;
+  B.b2 = B.hq2 * B.b1;
+  return B;
+}
+
+template <class real>
+DFW_HD void project(const Basis<real>& B, const real* w, real* q) {
+  real T = B.b2 * w[0] - B.b1 * (B.u * w[1] + B.v * w[2] - w[3]);
+  real s = (B.u * w[0] - w[1]) * B.ic;
+  q[0] = real(0.5) * (T + s);
+  q[1] = w[0] - T;
+  q[2] = w[2] - B.v * w[0];
+  q[3] = real(0.5) * (T - s);
+}
+
+template <class real>
+DFW_HD void unproject(const Basis<real>& B, const real* q, real* w) {
+  real w0 = q[0] + q[1] + q[3];
+  real dq = q[3] - q[0];
+  w[0] = w0;
+  w[1] = B.u * w0 + B.c * dq;
+  w[2] = B.v * w0 + q[2];
+  w[3] = B.H * (q[0] + q[3]) + B.u * B.c * dq + B.hq2 * q[1] + B.v * q[2];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Hybrid reconstruction of one cell (Section 3.1 and 3.3).  Q[0..4] = Q_{i-2..i+2}; the result is
+// the polynomial P(xi) = sum_n P[n] xi^n on the cell, xi = (x - x_{i+1/2})/dx in [-1, 0].
+//   WENO-AO: P = sum_{k<3} (wb_k - wb_3 d_k/d_3) p_k + (wb_3/d_3) p_3 with WENO-Z weights.
+//   DF branch (max of the three alphas < threshold): P = Q_i + alpha_i (p_1 - Q_i), which is the
+//   paper's zero-mean quadratic with x0 = -dx/2, x1 = dx^2/3 written through p_1.
+// NDEG limits the coefficients produced (2 = value and slope at the edge only).
+// ------------------------------------------------------------------------------------------------
+template <class real, int NDEG>
+DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, real* P) {
+  const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
+  // candidate p1 (centred quadratic): coefficients of 1, xi, xi^2
+  real p1_0 = (real(5) * Q2 + real(2) * Q3 - Q1) * real(1.0 / 6.0);
+  real p1_1 = Q3 - Q2;
+  real p1_2 = real(0.5) * (Q1 + Q3) - Q2;
+  real amax = a_lo > a_c ? a_lo : a_c;
+  amax = amax > a_hi ? amax : a_hi;
+  if (amax < k.alpha_thres) {
+    P[0] = Q2 + a_c * (p1_0 - Q2);
+    if (NDEG > 1) P[1] = a_c * p1_1;
+    if (NDEG > 2) P[2] = a_c * p1_2;
+    if (NDEG > 3) P[3] = real(0);
+    if (NDEG > 4) P[4] = real(0);
+    return;
+  }
+  real p0_0 = (real(2) * Q0 - real(7) * Q1 + real(11) * Q2) * real(1.0 / 6.0);
+  real p0_1 = Q0 - real(3) * Q1 + real(2) * Q2;
+  real p0_2 = real(0.5) * (Q0 + Q2) - Q1;
+  real p2_0 = (real(2) * Q2 + real(5) * Q3 - Q4) * real(1.0 / 6.0);
+  real p2_1 = Q3 - Q2;
+  real p2_2 = real(0.5) * (Q2 + Q4) - Q3;
+  real c0 = (real(2) * Q0 - real(13) * Q1 + real(47) * Q2 + real(27) * Q3 - real(3) * Q4) * real(1.0 / 60.0);
+  real c1 = (Q1 - real(15) * Q2 + real(15) * Q3 - Q4) * real(1.0 / 12.0);
+  real c2 = (-Q0 + real(6) * Q1 - real(8) * Q2 + real(2) * Q3 + Q4) * real(0.125);
+  real c3 = (-Q1 + real(3) * Q2 - real(3) * Q3 + Q4) * real(1.0 / 6.0);
+  real c4 = (Q0 - real(4) * Q1 + real(6) * Q2 - real(4) * Q3 + Q4) * real(1.0 / 24.0);
+  // smoothness indicators: Jiang-Shu forms for the quadratics, closed form for the quartic
+  const real k1312 = real(13.0 / 12.0), k14 = real(0.25);
+  real t;
+  t = Q0 - real(2) * Q1 + Q2;
+  real s = Q0 - real(4) * Q1 + real(3) * Q2;
+  real b0 = k1312 * t * t + k14 * s * s;
+  t = Q1 - real(2) * Q2 + Q3;
+  s = Q1 - Q3;
+  real b1 = k1312 * t * t + k14 * s * s;
+  t = Q2 - real(2) * Q3 + Q4;
+  s = real(3) * Q2 - real(4) * Q3 + Q4;
+  real b2 = k1312 * t * t + k14 * s * s;
+  real u1 = (real(11) * (Q0 - Q4) + real(82) * (Q3 - Q1)) * real(1.0 / 120.0);
+  real u2 = (real(40) * (Q1 + Q3) - real(3) * (Q0 + Q4) - real(74) * Q2) * real(1.0 / 56.0);
+  real u3 = (real(2) * (Q1 - Q3) + Q4 - Q0) * real(1.0 / 12.0);
+  real u4 = c4;
+  real e1 = u1 + real(0.1) * u3;
+  real e2 = u2 + real(123.0 / 455.0) * u4;
+  real b3 = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 +
+            real(1421461.0 / 2275.0) * u4 * u4;
+  // WENO-Z weights, eq. (37)
+  real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
+  real r0 = tau / (b0 + k.eps), r1 = tau / (b1 + k.eps), r2 = tau / (b2 + k.eps), r3 = tau / (b3 + k.eps);
+  real w0 = k.d[0] * (real(1) + r0 * r0);
+  real w1 = k.d[1] * (real(1) + r1 * r1);
+  real w2 = k.d[2] * (real(1) + r2 * r2);
+  real w3 = k.d[3] * (real(1) + r3 * r3);
+  real iws = real(1) / (w0 + w1 + w2 + w3);
+  real g3 = w3 * iws;
+  real g0 = w0 * iws - g3 * k.dr[0];
+  real g1 = w1 * iws - g3 * k.dr[1];
+  real g2 = w2 * iws - g3 * k.dr[2];
+  real h3 = g3 * k.inv_d3;
+  P[0] = g0 * p0_0 + g1 * p1_0 + g2 * p2_0 + h3 * c0;
+  if (NDEG > 1) P[1] = g0 * p0_1 + g1 * p1_1 + g2 * p2_1 + h3 * c1;
+  if (NDEG > 2) P[2] = g0 * p0_2 + g1 * p1_2 + g2 * p2_2 + h3 * c2;
+  if (NDEG > 3) P[3] = h3 * c3;
+  if (NDEG > 4) P[4] = h3 * c4;
+}
+
+// Gauss points of a segment [-1, 0] (in units of its length): -1/2 -+ sqrt(3)/6.
+constexpr double kXiGp0 = -0.5 - 0.28867513459481288225;
+constexpr double kXiGp1 = -0.5 + 0.28867513459481288225;
+
+template <class real>
+DFW_HD void eval_poly_at(const real* P, real xi, real& val, real& der) {
+  val = (((P[4] * xi + P[3]) * xi + P[2]) * xi + P[1]) * xi + P[0];
+  der = ((real(4) * P[4] * xi + real(3) * P[3]) * xi + real(2) * P[2]) * xi + P[1];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Primitive variables and the DF of one Gauss point (Section 3.2):
+//   alpha = 1/(1 + D^2), D = |pl-pr|/pl + |pl-pr|/pr + (Ma_n^l - Ma_n^r)^2 + (Ma_t^l - Ma_t^r)^2.
+// ------------------------------------------------------------------------------------------------
+template <class real>
+struct Prim {
+  real r, ir, u, v, p, c;
+};
+
+template <class real>
+DFW_HD Prim<real> prim(const real* w, const Coef<real>& k) {
+  Prim<real> q;
+  q.r = w[0];
+  q.ir = real(1) / w[0];
+  q.u = w[1] * q.ir;
+  q.v = w[2] * q.ir;
+  q.p = k.gm1 * (w[3] - real(0.5) * (w[1] * q.u + w[2] * q.v));
+  q.c = sqrt(k.gamma * q.p * q.ir);
+  return q;
+}
+
+template <class real>
+DFW_HD real df_factor(const Prim<real>& L, const Prim<real>& R) {
+  real jump = fabs(L.p - R.p);
+  real icl = real(1) / L.c, icr = real(1) / R.c;
+  real dn = L.u * icl - R.u * icr;
+  real dt = L.v * icl - R.v * icr;
+  real D = jump * (real(1) / L.p + real(1) / R.p) + dn * dn + dt * dt;
+  return real(1) / (real(1) + D * D);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Lax-Friedrichs flux (Section 2.3) and its time derivative for S2O4: the left and right time
+// derivatives come from the Euler equations in primitive form (Cauchy-Kovalevskaya),
+//   rho_t = -(u rho_x + rho u_x + v rho_y + rho v_y),  u_t = -(u u_x + v u_y + p_x/rho),
+//   v_t = -(u v_x + v v_y + p_y/rho),  p_t = -(u p_x + v p_y + gamma p (u_x + v_y)),
+// and dF/dt = (F_t^l + F_t^r)/2 - s (W_t^r - W_t^l)/2 with the LF speed s held fixed.
+// ------------------------------------------------------------------------------------------------
+template <class real>
+DFW_HD void euler_time_derivs(const real* w, const Prim<real>& q, const real* wx, const real* wy,
+                              const Coef<real>& k, real* wt, real* ft) {
+  real ke = real(0.5) * (q.u * q.u + q.v * q.v);
+  real ux = (wx[1] - q.u * wx[0]) * q.ir, vx = (wx[2] - q.v * wx[0]) * q.ir;
+  real px = k.gm1 * (wx[3] - q.u * wx[1] - q.v * wx[2] + ke * wx[0]);
+  real uy = (wy[1] - q.u * wy[0]) * q.ir, vy = (wy[2] - q.v * wy[0]) * q.ir;
+  real py = k.gm1 * (wy[3] - q.u * wy[1] - q.v * wy[2] + ke * wy[0]);
+  real rt = -(q.u * wx[0] + q.r * ux + q.v * wy[0] + q.r * vy);
+  real ut = -(q.u * ux + q.v * uy + px * q.ir);
+  real vt = -(q.u * vx + q.v * vy + py * q.ir);
+  real pt = -(q.u * px + q.v * py + k.gamma * q.p * (ux + vy));
+  wt[0] = rt;
+  wt[1] = rt * q.u + q.r * ut;
+  wt[2] = rt * q.v + q.r * vt;
+  wt[3] = pt * k.inv_gm1 + rt * ke + q.r * (q.u * ut + q.v * vt);
+  ft[0] = wt[1];
+  ft[1] = wt[1] * q.u + w[1] * ut + pt;
+  ft[2] = wt[1] * q.v + w[1] * vt;
+  ft[3] = ut * (w[3] + q.p) + q.u * (wt[3] + pt);
+}
+
+template <class real, bool WANT_F>
+DFW_HD void lf_flux(const real* wl, const real* wlx, const real* wly, const real* wr, const real* wrx,
+                    const real* wry, const Prim<real>& ql, const Prim<real>& qr, const Coef<real>& k,
+                    real* F, real* Ft) {
+  real sl = fabs(ql.u) + ql.c, sr = fabs(qr.u) + qr.c;
+  real s = sl >= sr ? sl : sr;
+  real hs = real(0.5) * s;
+  if (WANT_F) {
+    real Fl[4] = {wl[1], wl[1] * ql.u + ql.p, wl[2] * ql.u, ql.u * (wl[3] + ql.p)};
+    real Fr[4] = {wr[1], wr[1] * qr.u + qr.p, wr[2] * qr.u, qr.u * (wr[3] + qr.p)};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F[c] = real(0.5) * (Fl[c] + Fr[c]) - hs * (wr[c] - wl[c]);
+  }
+  real wtl[4], ftl[4], wtr[4], ftr[4];
+  euler_time_derivs(wl, ql, wlx, wly, k, wtl, ftl);
+  euler_time_derivs(wr, qr, wrx, wry, k, wtr, ftr);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Ft[c] = real(0.5) * (ftl[c] + ftr[c]) - hs * (wtr[c] - wtl[c]);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Gas-kinetic flux (Sections 2.2 and 3.4), Euler case: physical tau = 0 outside the exponential,
+// numerical tau_n = c1 dt + c2 |(pl-pr)/(pl+pr)| dt inside it.
+// Moments <u^a v^b xi^2c> of a Maxwellian (normalised by rho) factorise as mu[a] mv[b] mx[c].
+// ------------------------------------------------------------------------------------------------
+template <class real>
+struct Mom {
+  real mu[7];  // u-moments 0..6 (full space, or one half space)
+  real mv[6];  // v-moments 0..5 (full space)
+  real mx[3];  // <xi^0>, <xi^2>, <xi^4>
+  real U, V, lam;
+};
+
+template <class real>
+DFW_HD void full_recursion(real* m, int from, int to, real U, real h) {
+  // m[n+2] = U m[n+1] + (n+1) h m[n], h = 1/(2 lambda)
+  for (int n = from; n + 2 <= to; ++n) m[n + 2] = U * m[n + 1] + real(n + 1) * h * m[n];
+}
+
+// side: 0 full space, +1 u > 0, -1 u < 0
+template <class real>
+DFW_HD void maxwell_moments(real U, real V, real lam, int side, const Coef<real>& k, Mom<real>& M) {
+  M.U = U;
+  M.V = V;
+  M.lam = lam;
+  real h = real(0.5) / lam;
+  if (side == 0) {
+    M.mu[0] = real(1);
+    M.mu[1] = U;
+  } else {
+    const real inv_sqrt_pi = real(0.56418958354775628695);
+    real sl = sqrt(lam);
+    real g = real(0.5) * exp(-lam * U * U) * inv_sqrt_pi / sl;
+    if (side > 0) {
+      M.mu[0] = real(0.5) * erfc(-sl * U);
+      M.mu[1] = U * M.mu[0] + g;
+    } else {
+      M.mu[0] = real(0.5) * erfc(sl * U);
+      M.mu[1] = U * M.mu[0] - g;
+    }
+  }
+  full_recursion(M.mu, 0, 6, U, h);
+  M.mv[0] = real(1);
+  M.mv[1] = V;
+  full_recursion(M.mv, 0, 5, V, h);
+  M.mx[0] = real(1);
+  M.mx[1] = k.K * h;
+  M.mx[2] = k.K * (k.K + real(2)) * h * h;
+}
+
+template <class real>
+DFW_HD real mom(const Mom<real>& M, int a, int b, int c) {
+  return M.mu[a] * M.mv[b] * M.mx[c];
+}
+
+// <(s . psi) u^a v^b xi^2c>, s . psi = s0 + s1 u + s2 v + s3 (u^2 + v^2 + xi^2)/2
+template <class real>
+DFW_HD real mom_s(const Mom<real>& M, const real* s, int a, int b, int c) {
+  return s[0] * mom(M, a, b, c) + s[1] * mom(M, a + 1, b, c) + s[2] * mom(M, a, b + 1, c) +
+         real(0.5) * s[3] * (mom(M, a + 2, b, c) + mom(M, a, b + 2, c) + mom(M, a, b, c + 1));
+}
+
+// <(s . psi) u^a v^b psi>  (4 components)
+template <class real>
+DFW_HD void mom_s_psi(const Mom<real>& M, const real* s, int a, int b, real* out) {
+  out[0] = mom_s(M, s, a, b, 0);
+  out[1] = mom_s(M, s, a + 1, b, 0);
+  out[2] = mom_s(M, s, a, b + 1, 0);
+  out[3] = real(0.5) * (mom_s(M, s, a + 2, b, 0) + mom_s(M, s, a, b + 2, 0) + mom_s(M, s, a, b, 1));
+}
+
+// <u^a v^b psi>
+template <class real>
+DFW_HD void mom_psi(const Mom<real>& M, int a, int b, real* out) {
+  out[0] = mom(M, a, b, 0);
+  out[1] = mom(M, a + 1, b, 0);
+  out[2] = mom(M, a, b + 1, 0);
+  out[3] = real(0.5) * (mom(M, a + 2, b, 0) + mom(M, a, b + 2, 0) + mom(M, a, b, 1));
+}
+
+// Micro-slope s with <(s . psi) psi> = g (g = dW / rho), closed-form inverse of the moment matrix.
+template <class real>
+DFW_HD void micro_slope(const real* g, real U, real V, real lam, const Coef<real>& k, real* s) {
+  real B = U * U + V * V + (k.K + real(2)) * real(0.5) / lam;
+  real R4 = real(2) * g[3] - B * g[0];
+  real R3 = g[2] - V * g[0];
+  real R2 = g[1] - U * g[0];
+  s[3] = real(4) * lam * lam / (k.K + real(2)) * (R4 - real(2) * U * R2 - real(2) * V * R3);
+  s[2] = real(2) * lam * R3 - V * s[3];
+  s[1] = real(2) * lam * R2 - U * s[3];
+  s[0] = g[0] - U * s[1] - V * s[2] - real(0.5) * s[3] * B;
+}
+
+// GKS flux at one Gauss point.  wl/wr: states; wln/wrn: normal derivatives; wlt/wrt: tangential
+// derivatives.  Outputs F (if WANT_F) and dF/dt by the S2O4 fit of eq. (26) to the time
+// integrals over dt and dt/2, written in closed form:
+//   F    = cf1 Fc + cf2 (Ma_c - Ma_lr) + (1 - cf1) F_lr
+//   F_t  = ct1 (Fc - F_lr) + ct2 (Ma_c - Ma_lr) + MA_c
+// with E1 = exp(-dt/tau), E2 = exp(-dt/(2 tau)):
+//   cf1 = 1 - (tau/dt)(3 - 4E2 + E1),  cf2 = (tau^2/dt)(3 - 4E2 + E1) + tau (E1 - 2E2),
+//   ct1 = 4 tau (1 - E2)^2 / dt^2,     ct2 = 4 (tau dt E2 (1 - E2) - tau^2 (1 - E2)^2) / dt^2.
+template <class real, bool WANT_F>
+DFW_HD void gks_flux(const real* wl, const real* wln, const real* wlt, const real* wr, const real* wrn,
+                     const real* wrt, const Prim<real>& ql, const Prim<real>& qr, real dt,
+                     const Coef<real>& k, real* F, real* Ft) {
+  real Wc[4] = {0, 0, 0, 0}, Wcn[4] = {0, 0, 0, 0}, Wct[4] = {0, 0, 0, 0};
+  real Flr[4] = {0, 0, 0, 0}, Malr[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const real* w = side == 0 ? wl : wr;
+    const real* wn = side == 0 ? wln : wrn;
+    const real* wt = side == 0 ? wlt : wrt;
+    const Prim<real>& q = side == 0 ? ql : qr;
+    real lam = real(0.5) * q.r / q.p;
+    Mom<real> M;
+    maxwell_moments(q.u, q.v, lam, side == 0 ? 1 : -1, k, M);
+    real g[4], a[4], b[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g[c] = wn[c] * q.ir;
+    micro_slope(g, q.u, q.v, lam, k, a);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g[c] = wt[c] * q.ir;
+    micro_slope(g, q.u, q.v, lam, k, b);
+    real t0[4], t1[4], t2[4];
+    mom_psi(M, 0, 0, t0);
+    mom_s_psi(M, a, 0, 0, t1);
+    mom_s_psi(M, b, 0, 0, t2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      Wc[c] += q.r * t0[c];
+      Wcn[c] += q.r * t1[c];
+      Wct[c] += q.r * t2[c];
+    }
+    mom_psi(M, 1, 0, t0);
+    mom_s_psi(M, a, 2, 0, t1);
+    mom_s_psi(M, b, 1, 1, t2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      Flr[c] += q.r * t0[c];
+      Malr[c] += q.r * (t1[c] + t2[c]);
+    }
+  }
+  // equilibrium state at the interface
+  real irc = real(1) / Wc[0];
+  real Uc = Wc[1] * irc, Vc = Wc[2] * irc;
+  real pc = k.gm1 * (Wc[3] - real(0.5) * (Wc[1] * Uc + Wc[2] * Vc));
+  real lamc = real(0.5) * Wc[0] / pc;
+  Mom<real> M;
+  maxwell_moments(Uc, Vc, lamc, 0, k, M);
+  real g[4], ac[4], bc[4], Ac[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) g[c] = Wcn[c] * irc;
+  micro_slope(g, Uc, Vc, lamc, k, ac);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) g[c] = Wct[c] * irc;
+  micro_slope(g, Uc, Vc, lamc, k, bc);
+  // compatibility: <(A . psi) psi> = -<((a . psi) u + (b . psi) v) psi>
+  real t1[4], t2[4];
+  mom_s_psi(M, ac, 1, 0, t1);
+  mom_s_psi(M, bc, 0, 1, t2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) g[c] = -(t1[c] + t2[c]);
+  micro_slope(g, Uc, Vc, lamc, k, Ac);
+  real Fc[4], Mac[4], MAc[4];
+  mom_psi(M, 1, 0, Fc);
+  mom_s_psi(M, ac, 2, 0, t1);
+  mom_s_psi(M, bc, 1, 1, t2);
+  mom_s_psi(M, Ac, 1, 0, MAc);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    Fc[c] *= Wc[0];
+    Mac[c] = Wc[0] * (t1[c] + t2[c]);
+    MAc[c] *= Wc[0];
+  }
+  // time coefficients
+  real tau = k.c1 * dt + k.c2 * fabs((ql.p - qr.p) / (ql.p + qr.p)) * dt;
+  real E2 = exp(-real(0.5) * dt / tau);
+  real E1 = E2 * E2;
+  real om = real(1) - E2;
+  real idt = real(1) / dt;
+  real ct1 = real(4) * tau * om * om * idt * idt;
+  real ct2 = real(4) * (tau * dt * E2 * om - tau * tau * om * om) * idt * idt;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Ft[c] = ct1 * (Fc[c] - Flr[c]) + ct2 * (Mac[c] - Malr[c]) + MAc[c];
+  if (WANT_F) {
+    real z = real(3) - real(4) * E2 + E1;
+    real cf1 = real(1) - tau * idt * z;
+    real cf2 = tau * tau * idt * z + tau * (E1 - real(2) * E2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F[c] = cf1 * Fc[c] + cf2 * (Mac[c] - Malr[c]) + (real(1) - cf1) * Flr[c];
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// One interface segment, normal sweep (Section 3.1, Algorithm 1): from the six cells along the
+// normal (cells f-3..f+2 around interface f) and the DF of cells f-2..f+1, the line values of the
+// left state (cell f-1 at its right edge) and the right state (cell f at its left edge, mirrored
+// stencil) and their normal derivatives, in conservative variables.
+// ------------------------------------------------------------------------------------------------
+template <class real>
+DFW_HD void normal_sweep(const real (*cell)[4], real a0, real a1, real a2, real a3, real inv_dn,
+                         const Coef<real>& k, real* wl, real* wr, real* wln, real* wrn) {
+  Basis<real> B = make_basis(cell[2], cell[3], k);
+  real Q[6][4];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) project(B, cell[m], Q[m]);
+  real ql[4], qld[4], qr[4], qrd[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    real s[5], P2[2];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
+    recon_poly<real, 2>(s, a0, a1, a2, k, P2);
+    ql[c] = P2[0];
+    qld[c] = P2[1] * inv_dn;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s[m] = Q[5 - m][c];
+    recon_poly<real, 2>(s, a3, a2, a1, k, P2);
+    qr[c] = P2[0];
+    qrd[c] = -P2[1] * inv_dn;
+  }
+  unproject(B, ql, wl);
+  unproject(B, qr, wr);
+  unproject(B, qld, wln);
+  unproject(B, qrd, wrn);
+}
+
+// ------------------------------------------------------------------------------------------------
+// One interface segment, tangential sweep and fluxes: the basis of the segment from its two cells
+// (wa, wb); line(side, m, c) returns component c of the side's line value on segment row m-2..m+2;
+// alpha[side][0..2] are the DF of the same-side cells on rows -1, 0, +1.  Produces the sums over
+// the two Gauss points of the flux and its time derivative (quadrature weights applied by the
+// caller) and the product of the two Gauss-point DF values.
+// ------------------------------------------------------------------------------------------------
+template <class real, int FLUX, bool WANT_F, bool WANT_DF, class LineFn>
+DFW_HD void segment_fluxes(const real* wa, const real* wb, LineFn line, const real (*alpha)[3],
+                           const real* wln, const real* wrn, real dt, real inv_dt, const Coef<real>& k,
+                           real* Fs, real* Fts, real& dfp) {
+  Basis<real> B = make_basis(wa, wb, k);
+  real gw[2][2][4], gwt[2][2][4];  // [side][gauss point][component]
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    real Q[5][4];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      real w[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w[c] = line(side, m, c);
+      project(B, w, Q[m]);
+    }
+    real qv[2][4], qd[2][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      real s[5], Pc[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
+      recon_poly<real, 5>(s, alpha[side][0], alpha[side][1], alpha[side][2], k, Pc);
+      real v0, d0, v1, d1;
+      eval_poly_at(Pc, real(kXiGp0), v0, d0);
+      eval_poly_at(Pc, real(kXiGp1), v1, d1);
+      qv[0][c] = v0;
+      qv[1][c] = v1;
+      qd[0][c] = d0 * inv_dt;
+      qd[1][c] = d1 * inv_dt;
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      unproject(B, qv[g], gw[side][g]);
+      unproject(B, qd[g], gwt[side][g]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    Fs[c] = real(0);
+    Fts[c] = real(0);
+  }
+  dfp = real(1);
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    Prim<real> ql = prim(gw[0][g], k), qr = prim(gw[1][g], k);
+    real F[4], Ft[4];
+    if (FLUX == 0)
+      lf_flux<real, WANT_F>(gw[0][g], wln, gwt[0][g], gw[1][g], wrn, gwt[1][g], ql, qr, k, F, Ft);
+    else
+      gks_flux<real, WANT_F>(gw[0][g], wln, gwt[0][g], gw[1][g], wrn, gwt[1][g], ql, qr, dt, k, F, Ft);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (WANT_F) Fs[c] += F[c];
+      Fts[c] += Ft[c];
+    }
+    if (WANT_DF) dfp *= df_factor(ql, qr);
+  }
+}
+
+}  // namespace dfw

@@ -1,0 +1,100 @@
+"""The C ABI library loads on the host, exports every entry point that include/*.h declares, its
+structs match the header, and argument validation works without touching a GPU."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2402_10914_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(dfw_[a-z0-9_]+)\s*\(", txt, re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = _declared_functions()
+    assert "dfw_run" in names and "dfw_rhs" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(_lib.SIGNATURES), set(names) - set(_lib.SIGNATURES)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dfweno.h"\nint main(void){'
+                   'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dfw_grid), offsetof(dfw_grid, dx),'
+                   ' offsetof(dfw_grid, bc_y), sizeof(dfw_params), offsetof(dfw_params, c2),'
+                   ' offsetof(dfw_params, reserved)); return 0;}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(_lib.dfw_grid), _lib.dfw_grid.dx.offset, _lib.dfw_grid.bc_y.offset,
+            ctypes.sizeof(_lib.dfw_params), _lib.dfw_params.c2.offset, _lib.dfw_params.reserved.offset]
+    assert out == want
+
+
+def _grid(nx=8, ny=8):
+    return _lib.dfw_grid(nx, ny, 0.1, 0.1, 0, 0)
+
+
+def _params(**kw):
+    d = dict(gamma=1.4, cfl=0.5, dt_fixed=0.0, alpha_thres=0.5, d_h=0.85, d_l=0.85, eps_weno=1e-6, c1=0.01, c2=5.0,
+             flux=0, reserved=0)
+    d.update(kw)
+    return _lib.dfw_params(*[d[k] for k, _ in _lib.dfw_params._fields_])
+
+
+def test_workspace_bytes_host_only():
+    L = _lib.load()
+    g = _grid(100, 50)
+    b64 = L.dfw_workspace_bytes(ctypes.byref(g), 0)
+    b32 = L.dfw_workspace_bytes(ctypes.byref(g), 1)
+    n = 100 * 50
+    assert b64 >= 8 * (8 * n + 9 * (50 * 101 + 51 * 100))
+    assert b32 < b64
+    assert L.dfw_workspace_bytes(ctypes.byref(_grid(0, 5)), 0) == 0
+
+
+@pytest.mark.parametrize("case,status", [
+    (dict(grid=_grid(0, 4)), _lib.DFW_EINVAL),
+    (dict(params=_params(gamma=1.0)), _lib.DFW_EINVAL),
+    (dict(params=_params(flux=7)), _lib.DFW_EINVAL),
+    (dict(params=_params(cfl=0.0, dt_fixed=0.0)), _lib.DFW_EINVAL),
+    (dict(params=_params(reserved=1)), _lib.DFW_EINVAL),
+    (dict(dtype=5), _lib.DFW_EDTYPE),
+    (dict(W=None), _lib.DFW_EINVAL),
+    (dict(nsteps=-1), _lib.DFW_EINVAL),
+    (dict(ws=None), _lib.DFW_EWORKSPACE),
+    (dict(ws=257), _lib.DFW_EWORKSPACE),
+    (dict(ws_bytes=16), _lib.DFW_EWORKSPACE),
+])
+def test_run_validation_without_gpu(case, status):
+    L = _lib.load()
+    a = dict(W=4096, alpha=8192, grid=_grid(), params=_params(), nsteps=1, dtype=0, ws=1 << 20, ws_bytes=1 << 30)
+    a.update(case)
+    st = L.dfw_run(a["W"], a["alpha"], ctypes.byref(a["grid"]), ctypes.byref(a["params"]), a["nsteps"], a["dtype"],
+                   a["ws"], a["ws_bytes"], None, None, None, None)
+    assert st == status
+    assert len(L.dfw_last_error()) > 0
+
+
+def test_rhs_and_speed_validation_without_gpu():
+    L = _lib.load()
+    g, p = _grid(), _params()
+    assert L.dfw_rhs(4096, 8192, ctypes.byref(g), ctypes.byref(p), 0, 0.0, 4096, 4096, None, 1 << 20, 1 << 30,
+                     None) == _lib.DFW_EINVAL
+    assert L.dfw_max_speed(None, ctypes.byref(g), ctypes.byref(p), 0, 1 << 20, 1 << 30, None, None,
+                           None) == _lib.DFW_EINVAL

@@ -1,0 +1,175 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on small and ragged grids.
+
+Tolerance: relative L1 (sum|gpu - oracle| / sum|oracle|, per component, maximum over components)
+<= 1e-12 in FP64 and <= 1e-5 for the FP32 path against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2402_10914_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+def rel_l1(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.ndim == 2:
+        a, b = a[None], b[None]
+    return max(float(np.abs(a[c] - b[c]).sum() / max(np.abs(b[c]).sum(), 1e-300)) for c in range(a.shape[0]))
+
+
+def _api():
+    from paper_2402_10914_amd import api
+    return api
+
+
+def gpu_params(flux, **kw):
+    return _api().Params(flux=flux, **kw)
+
+
+def ora_params(flux, **kw):
+    return O.make_params(flux=flux, **kw)
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def stepper(prob, params, dtype=torch.float64):
+    return _api().Stepper(prob.nx, prob.ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y, params, dtype)
+
+
+def ogrid(prob):
+    return O.make_grid(prob.nx, prob.ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y)
+
+
+def _rand_alpha(shape, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 1.0, shape)
+    a[rng.uniform(size=shape) < 0.5] = 1.0
+    return a
+
+
+CASES = [
+    ("riemann", 37, 23), ("riemann", 16, 16), ("riemann", 5, 40), ("riemann", 64, 3),
+    ("circles", 40, 40), ("circles", 29, 51), ("riemann", 1, 9), ("riemann", 30, 1),
+]
+
+
+def _problem(kind, nx, ny, seed=5):
+    if kind == "riemann":
+        return WL.riemann4(nx, ny, seed=seed)
+    if kind == "circles":
+        pr = WL.circles(max(nx, ny), seed=seed, ncirc=4)
+        pr.W = np.ascontiguousarray(pr.W[:, :ny, :nx])
+        pr.alpha = np.ones((ny, nx))
+        pr.nx, pr.ny = nx, ny
+        return pr
+    return WL.density_wave(nx, ny)
+
+
+def scaled_l1(Lt_g, Lt_o, L_o, dt):
+    """dL/dt enters the state only as dt^2 L_t next to dt L (eq. (24)), so its error is measured
+    on that scale: sum|dt (Lt_g - Lt_o)| / (sum|L_o| + sum|dt Lt_o|), per component.  (Where the
+    fluxes are nearly piecewise constant dL/dt is a cancellation of much larger terms.)"""
+    return max(float(dt * np.abs(Lt_g[c] - Lt_o[c]).sum() / (np.abs(L_o[c]).sum() + dt * np.abs(Lt_o[c]).sum()))
+               for c in range(4))
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+@pytest.mark.parametrize("alpha_kind", ["random", "one"])
+@pytest.mark.parametrize("kind,nx,ny", CASES)
+def test_rhs_parity(kind, nx, ny, flux, alpha_kind):
+    pr = _problem(kind, nx, ny)
+    alpha = _rand_alpha((ny, nx), nx * 31 + ny) if alpha_kind == "random" else np.ones((ny, nx))
+    dt = 1e-3
+    L0, Lt0, a0 = O.rhs(pr.W, alpha, ogrid(pr), ora_params(flux), dt, want_alpha=True)
+    st = stepper(pr, gpu_params(flux))
+    L1, Lt1, a1 = st.rhs(to_dev(pr.W), to_dev(alpha), dt, want_alpha=True)
+    torch.cuda.synchronize()
+    assert rel_l1(L1.cpu().numpy(), L0) <= TOL64
+    assert scaled_l1(Lt1.cpu().numpy(), Lt0, L0, dt) <= TOL64
+    assert rel_l1(a1.cpu().numpy(), a0) <= TOL64
+
+
+def _run_pair(pr, flux, nsteps, cfl, dtype=torch.float64, **kw):
+    Wo, ao, to, dto, fso = O.run(pr.W, pr.alpha, ogrid(pr), ora_params(flux, cfl=cfl, **kw), nsteps)
+    st = stepper(pr, gpu_params(flux, cfl=cfl, **kw), dtype)
+    W = to_dev(pr.W, dtype)
+    A = to_dev(pr.alpha, dtype)
+    dth = torch.zeros(max(nsteps, 1), dtype=torch.float64, device="cuda")
+    t, fs = st.run(W, A, nsteps, dt_hist=dth)
+    torch.cuda.synchronize()
+    return (Wo, ao, to, dto, fso), (W.double().cpu().numpy(), A.double().cpu().numpy(), t, dth.cpu().numpy()[:nsteps], fs)
+
+
+def test_density_wave_c1_parity_and_exact_solution():
+    """64x64 density wave, LF, CFL 0.5, 20 steps (the small configuration)."""
+    pr = WL.density_wave(64, flux=0, cfl=0.5, nsteps=20)
+    (Wo, ao, to, dto, fso), (Wg, ag, tg, dtg, fsg) = _run_pair(pr, 0, 20, 0.5)
+    assert fso == -1 and fsg == -1
+    assert rel_l1(Wg, Wo) <= TOL64
+    assert rel_l1(ag, ao) <= TOL64
+    np.testing.assert_allclose(dtg, dto, rtol=1e-14)
+    assert abs(tg - to) <= 1e-14 * to
+    err = np.abs(Wg[0] - WL.density_wave_avg(64, 64, t=tg)).mean()
+    assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+@pytest.mark.parametrize("nx,ny", [(48, 40), (33, 17)])
+def test_riemann_run_parity(flux, nx, ny):
+    pr = WL.riemann4(nx, ny, seed=11)
+    (Wo, ao, to, dto, fso), (Wg, ag, tg, dtg, fsg) = _run_pair(pr, flux, 25, 0.4)
+    assert fso == -1 and fsg == -1
+    assert rel_l1(Wg, Wo) <= TOL64
+    assert rel_l1(ag, ao) <= TOL64
+    np.testing.assert_allclose(dtg, dto, rtol=1e-12)
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_fp32_parity(flux):
+    pr = WL.riemann4(40, 40, seed=3)
+    (Wo, ao, to, dto, fso), (Wg, ag, tg, dtg, fsg) = _run_pair(pr, flux, 20, 0.4, dtype=torch.float32)
+    assert fsg == -1
+    assert rel_l1(Wg, Wo) <= TOL32
+    assert rel_l1(ag, ao) <= 1e-4  # alpha is a product of 8 factors near discontinuities
+
+
+def test_max_speed_and_nonphysical():
+    pr = WL.riemann4(30, 20, seed=9)
+    s_o, ok = O.max_speed(pr.W, ogrid(pr), ora_params(0))
+    st = stepper(pr, gpu_params(0))
+    s_g, bad = st.max_speed(to_dev(pr.W))
+    assert ok and not bad
+    assert s_g == pytest.approx(s_o, rel=1e-14)
+    W = pr.W.copy()
+    W[3, 4, 7] = -1.0
+    s_g, bad = st.max_speed(to_dev(W))
+    assert bad
+    t, fs = st.run(to_dev(W), to_dev(pr.alpha), 3)
+    assert fs == 0
+
+
+def test_bitwise_determinism_and_transpose():
+    pr = WL.riemann4(36, 36, seed=21)
+    st = stepper(pr, gpu_params(1, cfl=0.4))
+    outs = []
+    for _ in range(2):
+        W = to_dev(pr.W)
+        A = to_dev(pr.alpha)
+        st.run(W, A, 8)
+        outs.append((W.cpu().numpy(), A.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    Wt = np.stack([pr.W[0].T, pr.W[2].T, pr.W[1].T, pr.W[3].T]).copy()
+    W = to_dev(Wt)
+    A = to_dev(pr.alpha.T.copy())
+    st.run(W, A, 8)
+    B = W.cpu().numpy()
+    Bt = np.stack([B[0].T, B[2].T, B[1].T, B[3].T])
+    assert np.array_equal(Bt, outs[0][0])
+    assert np.array_equal(A.cpu().numpy().T, outs[0][1])
