@@ -58,11 +58,12 @@ typedef struct {
  *   d_h, d_l     linear-weight parameters of WENO-AO (Section 3.1) [0.85, 0.85]
  *   eps_weno     epsilon of the WENO-Z weights (not given by the paper) [1e-6]
  *   c1, c2       numerical collision time tau_n = c1 dt + c2 |(pl-pr)/(pl+pr)| dt (Section 2.2) [0.01, 5]
- *   flux         DFW_FLUX_LF or DFW_FLUX_GKS */
+ *   flux         DFW_FLUX_LF or DFW_FLUX_GKS
+ *   tile         interface tile shape, 0 <= tile < dfw_num_tiles() [0]; results do not depend on it */
 typedef struct {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
-  int32_t reserved; /* must be 0 */
+  int32_t tile;
 } dfw_params;
 
 /* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */
@@ -93,6 +94,41 @@ dfw_status dfw_rhs(const void* W, const void* alpha, const dfw_grid* grid, const
                    int32_t dtype, double dt, void* L, void* Lt, void* alpha_new, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* ---- Batched ragged grids ---------------------------------------------------------------------
+ * Many independent grids (own sizes, spacing, boundaries and CFL time steps; one dfw_params for
+ * all) advanced together: every kernel launch covers the interfaces or cells of all grids, and
+ * dfw_batch_run can capture the whole nsteps rollout once into a hipGraph and replay it with one
+ * launch.  The states are packed back to back: grid g's W ([4][ny_g][nx_g]) starts at element
+ * w_offsets[g] of W_flat and its alpha at a_offsets[g] of alpha_flat (dfw_batch_layout). */
+typedef struct dfw_batch dfw_batch;
+
+/* Sweep order of the interface tiles of a batch (an autotuning knob; results do not depend on it). */
+enum { DFW_ORDER_GRID = 0, DFW_ORDER_LARGEST_FIRST = 1, DFW_ORDER_INTERLEAVED = 2 };
+
+/* Builds the descriptor and tile tables (host and a small device copy owned by the plan). */
+dfw_status dfw_batch_plan(const dfw_grid* grids, int32_t ngrids, const dfw_params* params, int32_t dtype,
+                          int32_t order, dfw_batch** out);
+
+/* Offsets (elements, host arrays of ngrids, may be NULL) and total sizes of the packed layout and
+ * the workspace the plan needs. */
+dfw_status dfw_batch_layout(const dfw_batch* b, int64_t* w_offsets, int64_t* a_offsets, size_t* w_elems,
+                            size_t* a_elems, size_t* ws_bytes);
+
+/* Advances every grid by nsteps S2O4 steps in place.  use_graph != 0 replays a hipGraph captured
+ * at the first call with these pointers and nsteps (re-captured when they change).
+ *   dt_hist_dev  device, optional: [ngrids][nsteps] FP64 time increments.
+ *   t_out        host, optional: [ngrids] simulated time of each grid.
+ *   fail_steps   host, optional: [ngrids] -1 or the completed steps when that grid met a
+ *                non-physical state (the other grids continue); returns DFW_ENONPHYS if any. */
+dfw_status dfw_batch_run(dfw_batch* b, void* W_flat, void* alpha_flat, int32_t nsteps, void* ws, size_t ws_bytes,
+                         int32_t use_graph, double* dt_hist_dev, double* t_out, int32_t* fail_steps, void* stream);
+
+void dfw_batch_free(dfw_batch* b);
+
+/* Interface tile shapes available for dfw_params.tile: TF interfaces by TR segments. */
+int32_t dfw_num_tiles(void);
+dfw_status dfw_tile_shape(int32_t tile, int32_t* tf, int32_t* tr);
+
 /* Measurement support: per-kernel device time of the launches made by dfw_run, recorded with HIP
  * events on the stream the kernels run on.  Kernel kinds index the arrays of dfw_profile_read. */
 enum {
@@ -101,7 +137,8 @@ enum {
   DFW_K_FACES2 = 2,   /* interface kernel, second stage (time derivative and DF) */
   DFW_K_UPDATE2 = 3,  /* cell kernel, second stage (W^{n+1}, alpha^{n+1}, CFL reduction) */
   DFW_K_SPEED = 4,    /* standalone CFL reduction of the input state */
-  DFW_K_COUNT = 5
+  DFW_K_GRAPH = 5,    /* one replay of a captured batched rollout */
+  DFW_K_COUNT = 6
 };
 
 /* enable != 0 clears the records and starts recording; 0 stops.  Process-wide, not thread-safe;

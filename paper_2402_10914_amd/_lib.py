@@ -16,7 +16,8 @@ DFW_OK, DFW_EINVAL, DFW_EDTYPE, DFW_EWORKSPACE, DFW_EHIP, DFW_ENONPHYS = range(6
 DFW_FLUX_LF, DFW_FLUX_GKS = 0, 1
 DFW_BC_PERIODIC, DFW_BC_TRANSMISSIVE = 0, 1
 DFW_F64, DFW_F32 = 0, 1
-KERNEL_KINDS = ["faces1", "update1", "faces2", "update2", "speed"]
+KERNEL_KINDS = ["faces1", "update1", "faces2", "update2", "speed", "graph"]
+DFW_ORDER_GRID, DFW_ORDER_LARGEST_FIRST, DFW_ORDER_INTERLEAVED = 0, 1, 2
 
 
 class dfw_grid(ctypes.Structure):
@@ -28,7 +29,7 @@ class dfw_params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
                 ("alpha_thres", ctypes.c_double), ("d_h", ctypes.c_double), ("d_l", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
-                ("flux", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flux", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class DFWError(RuntimeError):
@@ -53,6 +54,16 @@ SIGNATURES = {
     "dfw_max_speed": (ctypes.c_int32, [_VP, _GP, _PP, ctypes.c_int32, _VP, ctypes.c_size_t, _DP, _IP, _VP]),
     "dfw_rhs": (ctypes.c_int32, [_VP, _VP, _GP, _PP, ctypes.c_int32, ctypes.c_double, _VP, _VP, _VP, _VP,
                                  ctypes.c_size_t, _VP]),
+    "dfw_batch_plan": (ctypes.c_int32, [_GP, ctypes.c_int32, _PP, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "dfw_batch_layout": (ctypes.c_int32, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "dfw_batch_run": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.c_int32, _VP, ctypes.c_size_t, ctypes.c_int32, _VP,
+                                       _DP, _IP, _VP]),
+    "dfw_batch_free": (None, [_VP]),
+    "dfw_num_tiles": (ctypes.c_int32, []),
+    "dfw_tile_shape": (ctypes.c_int32, [ctypes.c_int32, _IP, _IP]),
     "dfw_profile": (ctypes.c_int32, [ctypes.c_int32]),
     "dfw_profile_read": (ctypes.c_int32, [_DP, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "dfw_last_error": (ctypes.c_char_p, []),

@@ -34,11 +34,23 @@ class Params:
     eps_weno: float = 1e-6
     c1: float = 0.01
     c2: float = 5.0
+    tile: int = 0  # interface tile shape (performance only; see tile_shapes())
 
     def struct(self) -> _lib.dfw_params:
         return _lib.dfw_params(float(self.gamma), float(self.cfl), float(self.dt_fixed), float(self.alpha_thres),
                                float(self.d_h), float(self.d_l), float(self.eps_weno), float(self.c1),
-                               float(self.c2), int(self.flux), 0)
+                               float(self.c2), int(self.flux), int(self.tile))
+
+
+def tile_shapes():
+    """[(TF, TR)] of the interface tile shapes the library provides (index = Params.tile)."""
+    L = _lib.load()
+    out = []
+    for k in range(L.dfw_num_tiles()):
+        tf, tr = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(L.dfw_tile_shape(k, ctypes.byref(tf), ctypes.byref(tr)))
+        out.append((tf.value, tr.value))
+    return out
 
 
 def _dtype_code(dt: torch.dtype) -> int:
@@ -130,6 +142,75 @@ class Stepper:
                                     float(dt), _ptr(L), _ptr(Lt), _ptr(an) if an is not None else None,
                                     self.ws_ptr, self.ws_bytes, _stream_ptr(self.device)))
         return (L, Lt, an) if want_alpha else (L, Lt)
+
+
+class Batch:
+    """Many independent grids advanced together (one launch per kernel for all grids; optionally
+    one hipGraph replay for the whole rollout).  grids: list of (nx, ny, dx, dy, bc_x, bc_y)."""
+
+    def __init__(self, grids, params: Params, dtype: torch.dtype = torch.float64, order: int = 0, device="cuda"):
+        self.lib = _lib.load()
+        self.ngrids = len(grids)
+        arr = (_lib.dfw_grid * self.ngrids)(*[_lib.dfw_grid(int(nx), int(ny), float(dx), float(dy), int(bx), int(by))
+                                              for nx, ny, dx, dy, bx, by in grids])
+        self.grids = [tuple(g) for g in grids]
+        self.params = params
+        self.dtype = dtype
+        self.code = _dtype_code(dtype)
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        p = params.struct()
+        _lib.check(self.lib.dfw_batch_plan(arr, self.ngrids, ctypes.byref(p), self.code, int(order), ctypes.byref(h)))
+        self.handle = h
+        wo = (ctypes.c_int64 * self.ngrids)()
+        ao = (ctypes.c_int64 * self.ngrids)()
+        we, ae, wb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _lib.check(self.lib.dfw_batch_layout(h, wo, ao, ctypes.byref(we), ctypes.byref(ae), ctypes.byref(wb)))
+        self.w_offsets = list(wo)
+        self.a_offsets = list(ao)
+        self.w_elems, self.a_elems, self.ws_bytes = we.value, ae.value, wb.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + (-self.ws.data_ptr()) % 256)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.dfw_batch_free(h)
+            self.handle = None
+
+    def pack(self, Ws, alphas):
+        """Host or device arrays per grid -> packed device tensors (W_flat, alpha_flat)."""
+        Wf = torch.empty(self.w_elems, dtype=self.dtype, device=self.device)
+        Af = torch.empty(self.a_elems, dtype=self.dtype, device=self.device)
+        for g, (nx, ny, *_rest) in enumerate(self.grids):
+            n = nx * ny
+            Wf[self.w_offsets[g]:self.w_offsets[g] + 4 * n] = torch.as_tensor(Ws[g], dtype=self.dtype).reshape(-1).to(self.device)
+            Af[self.a_offsets[g]:self.a_offsets[g] + n] = torch.as_tensor(alphas[g], dtype=self.dtype).reshape(-1).to(self.device)
+        return Wf, Af
+
+    def unpack(self, Wf, Af):
+        out = []
+        for g, (nx, ny, *_rest) in enumerate(self.grids):
+            n = nx * ny
+            out.append((Wf[self.w_offsets[g]:self.w_offsets[g] + 4 * n].view(4, ny, nx),
+                        Af[self.a_offsets[g]:self.a_offsets[g] + n].view(ny, nx)))
+        return out
+
+    def run(self, Wf: torch.Tensor, Af: torch.Tensor, nsteps: int, use_graph: bool = True,
+            dt_hist: torch.Tensor | None = None):
+        """Advance every grid in place.  Returns (t per grid, fail step per grid)."""
+        if Wf.numel() != self.w_elems or Af.numel() != self.a_elems or Wf.dtype != self.dtype or Af.dtype != self.dtype:
+            raise ValueError("packed arrays do not match the plan")
+        if dt_hist is not None and (dt_hist.dtype != torch.float64 or dt_hist.numel() < self.ngrids * nsteps):
+            raise ValueError("dt_hist must be float64 with ngrids * nsteps entries")
+        t = (ctypes.c_double * self.ngrids)()
+        fs = (ctypes.c_int32 * self.ngrids)()
+        st = self.lib.dfw_batch_run(self.handle, _ptr(Wf), _ptr(Af), int(nsteps), self.ws_ptr, self.ws_bytes,
+                                    1 if use_graph else 0, _ptr(dt_hist) if dt_hist is not None else None, t, fs,
+                                    _stream_ptr(self.device))
+        if st not in (DFW_OK, DFW_ENONPHYS):
+            _lib.check(st)
+        return list(t), list(fs)
 
 
 class KernelProfile:

@@ -1,21 +1,23 @@
 // HIP kernels and C ABI of the S2O4 DF-hybrid step for gfx950 (Zhang, Ji & Xu, arXiv:2402.10914).
 //
 // One step = [faces(stage 1)] [update 1] [faces(stage 2)] [update 2]:
-//   faces:   one launch covers every x- and y-interface.  A workgroup owns a tile of TF interfaces
-//            (along the normal) by TR interface segments (along the tangential direction).  It
-//            stages the (TF+5) x (TR+4) cells and the alpha halo in LDS once (ghost cells by index
-//            mapping), runs the normal reconstruction for TR+4 segments per interface column into
-//            LDS, then the tangential reconstruction at the two Gauss points of each of its TR
-//            segments, the flux and its time derivative, and the DF of the Gauss points.  The
-//            thread that reconstructs a segment in the normal sweep also owns it in the
-//            tangential sweep, so the normal derivatives stay in registers.
+//   faces:   one launch covers every x- and y-interface (of one grid, or of every grid of a batch).
+//            A workgroup owns a tile of TF interfaces (along the normal) by TR interface segments
+//            (along the tangential direction).  It stages the (TF+5) x (TR+4) cells and the alpha
+//            halo in LDS once (ghost cells by index mapping), runs the normal reconstruction for
+//            TR+4 segments per interface column into LDS, then the tangential reconstruction at
+//            the two Gauss points of each of its TR segments, the flux and its time derivative, and
+//            the DF of the Gauss points.  The thread that reconstructs a segment in the normal sweep
+//            also owns it in the tangential sweep, so the normal derivatives stay in registers.
 //   update:  one thread per cell assembles L and dL/dt from the four face sums (eq. (2)) and
 //            applies eq. (24); the second update also forms alpha^{n+1} (Section 3.2), checks
 //            positivity and reduces the signal speed for the next dt (wavefront shuffle, LDS,
 //            one 64-bit atomic max per workgroup on the bit pattern of a non-negative double).
-// dt lives in device memory; the host never reads it inside a run.
+// Every grid has its own control block (dt, time, status), so the grids of a batch advance with
+// their own time steps; dt lives in device memory and the host never reads it inside a run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -29,7 +31,7 @@
 namespace dfw {
 
 // ------------------------------------------------------------------------------------------------
-// Device control block (in the workspace).
+// Device-side descriptions.
 // ------------------------------------------------------------------------------------------------
 struct Ctrl {
   unsigned long long smax_bits[2];  // running max signal speed / dx for the next step (ping-pong)
@@ -40,9 +42,18 @@ struct Ctrl {
   int pad[2];
 };
 
-struct KParams {
+// One grid: sizes, spacing, boundaries and element offsets of its arrays inside the (packed) state,
+// alpha, stage and interface buffers.
+struct GridDesc {
   int nx, ny, bc_x, bc_y;
   double dx, dy, inv_dx, inv_dy;
+  long long w_off;   // W, W*, R: [4][ny][nx] at this offset
+  long long a_off;   // alpha: [ny][nx]
+  long long fx_off;  // x-interface data: [9][ny][nx+1]
+  long long fy_off;  // y-interface data: [9][ny+1][nx]
+};
+
+struct Scheme {
   double gamma, cfl, dt_fixed, alpha_thres, eps, c1, c2, K;
   double d[4];
 };
@@ -50,19 +61,19 @@ struct KParams {
 enum { OUT_F = 1, OUT_FT = 2, OUT_DF = 4 };
 
 template <class real>
-__device__ __forceinline__ Coef<real> make_coef(const KParams& P) {
+__device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
   Coef<real> k;
-  k.gamma = real(P.gamma);
-  k.gm1 = real(P.gamma - 1.0);
-  k.inv_gm1 = real(1.0 / (P.gamma - 1.0));
-  k.alpha_thres = real(P.alpha_thres);
-  k.eps = real(P.eps);
-  k.c1 = real(P.c1);
-  k.c2 = real(P.c2);
-  k.K = real(P.K);
-  for (int i = 0; i < 4; ++i) k.d[i] = real(P.d[i]);
-  for (int i = 0; i < 3; ++i) k.dr[i] = real(P.d[i] / P.d[3]);
-  k.inv_d3 = real(1.0 / P.d[3]);
+  k.gamma = real(S.gamma);
+  k.gm1 = real(S.gamma - 1.0);
+  k.inv_gm1 = real(1.0 / (S.gamma - 1.0));
+  k.alpha_thres = real(S.alpha_thres);
+  k.eps = real(S.eps);
+  k.c1 = real(S.c1);
+  k.c2 = real(S.c2);
+  k.K = real(S.K);
+  for (int i = 0; i < 4; ++i) k.d[i] = real(S.d[i]);
+  for (int i = 0; i < 3; ++i) k.dr[i] = real(S.d[i] / S.d[3]);
+  k.inv_d3 = real(1.0 / S.d[3]);
   return k;
 }
 
@@ -75,65 +86,95 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// Face kernel.
-// Face arrays: FX [9][ny][nx+1] and FY [9][ny+1][nx]; entries 0..3 = face-averaged flux (global
-// components), 4..7 = its time derivative, 8 = product of the DF of the two Gauss points.
+// Interface kernel.
+// Interface data: entries 0..3 = face-averaged flux (global components), 4..7 = its time
+// derivative, 8 = product of the DF of the two Gauss points.
+// Tile entry (batch form): x = grid, y = dir | (lead tile of its grid) << 1, z = f0, w = t0.
 // ------------------------------------------------------------------------------------------------
 template <int TF, int TR>
 struct Tile {
-  static constexpr int NR = TR + 4;         // segments incl. the normal-sweep halo
-  static constexpr int NT = TF * NR;        // threads per workgroup
-  static constexpr int WN = TF + 5;         // cells along the normal
-  static constexpr int AN = TF + 3;         // alpha cells along the normal
+  static constexpr int NR = TR + 4;   // segments incl. the normal-sweep halo
+  static constexpr int NT = TF * NR;  // threads per workgroup
+  static constexpr int WN = TF + 5;   // cells along the normal
+  static constexpr int AN = TF + 3;   // alpha cells along the normal
 };
 
+template <int TF, int TR>
+__host__ __device__ inline int tiles_x(int nx, int ny) { return ((nx + 1 + TF - 1) / TF) * ((ny + TR - 1) / TR); }
+
 template <class real, int FLUX, int OUT, int TF, int TR>
-__global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict__ W,
-                                                              const real* __restrict__ alpha,
-                                                              real* __restrict__ FX, real* __restrict__ FY,
-                                                              Ctrl* __restrict__ ctrl, KParams P, double dt_host,
-                                                              int lead, int step, double* __restrict__ dt_hist) {
+__global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict__ Wall, const real* __restrict__ Aall,
+                                                         real* __restrict__ FXall, real* __restrict__ FYall,
+                                                         Ctrl* __restrict__ ctrls, GridDesc G0,
+                                                         const GridDesc* __restrict__ grids,
+                                                         const int4* __restrict__ tiles, Scheme S, double dt_host,
+                                                         int lead, int step, int nsteps, double* __restrict__ dt_hist) {
   using T = Tile<TF, TR>;
-  if (ctrl->status) return;
   __shared__ real sW[4][T::NR][T::WN];
   __shared__ real sA[T::NR][T::AN];
   __shared__ real sLine[8][T::NT];
 
-  const int nx = P.nx, ny = P.ny;
-  // ---- which tile: x-interfaces first, then y-interfaces
-  const int ntfx = (nx + 1 + TF - 1) / TF, ntrx = (ny + TR - 1) / TR;
-  const int nbx = ntfx * ntrx;
-  int b = blockIdx.x;
-  const int dir = b < nbx ? 0 : 1;
-  if (dir) b -= nbx;
+  // ---- which grid and tile
+  int gi = 0, dir, f0, t0;
+  bool lead_tile;
+  GridDesc G;
+  if (tiles) {
+    const int4 e = tiles[blockIdx.x];
+    gi = e.x;
+    dir = e.y & 1;
+    lead_tile = (e.y >> 1) & 1;
+    f0 = e.z;
+    t0 = e.w;
+    G = grids[gi];
+  } else {
+    G = G0;
+    int b = blockIdx.x;
+    const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
+    dir = b < nbx ? 0 : 1;
+    if (dir) b -= nbx;
+    const int ntf = dir ? (G.ny + 1 + TF - 1) / TF : (G.nx + 1 + TF - 1) / TF;
+    f0 = (b % ntf) * TF;
+    t0 = (b / ntf) * TR;
+    lead_tile = blockIdx.x == 0;
+  }
+  Ctrl* ctrl = ctrls + gi;
+  if (ctrl->status) return;
+  const int nx = G.nx, ny = G.ny;
+  const real* W = Wall + G.w_off;
+  const real* alpha = Aall + G.a_off;
+  real* FX = FXall + G.fx_off;
+  real* FY = FYall + G.fy_off;
   const int Nn = dir ? ny : nx, Nt = dir ? nx : ny;
-  const int ntf = dir ? (ny + 1 + TF - 1) / TF : ntfx;
-  const int f0 = (b % ntf) * TF, t0 = (b / ntf) * TR;
-  const int bcn = dir ? P.bc_y : P.bc_x, bct = dir ? P.bc_x : P.bc_y;
-  const real inv_dn = real(dir ? P.inv_dy : P.inv_dx), inv_dt = real(dir ? P.inv_dx : P.inv_dy);
+  const int bcn = dir ? G.bc_y : G.bc_x, bct = dir ? G.bc_x : G.bc_y;
+  const real inv_dn = real(dir ? G.inv_dy : G.inv_dx), inv_dt = real(dir ? G.inv_dx : G.inv_dy);
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
 
   // ---- dt of this step
   double dtd;
   if (dt_host > 0.0) dtd = dt_host;
-  else if (lead) dtd = P.cfl / __longlong_as_double((long long)ctrl->smax_bits[step & 1]);
+  else if (lead) dtd = S.cfl / __longlong_as_double((long long)ctrl->smax_bits[step & 1]);
   else dtd = ctrl->dt;
-  if (lead && blockIdx.x == 0 && tid == 0) {
+  if (lead && lead_tile && tid == 0) {
     ctrl->dt = dtd;
     ctrl->t += dtd;
     ctrl->smax_bits[(step + 1) & 1] = 0ull;
-    if (dt_hist) dt_hist[step] = dtd;
+    if (dt_hist) dt_hist[(size_t)gi * nsteps + step] = dtd;
   }
   const real dt = real(dtd);
-  const Coef<real> k = make_coef<real>(P);
+  const Coef<real> k = make_coef<real>(S);
 
   // ---- stage cells and alpha into LDS (ghost cells by index mapping); component order local:
   //      0 rho, 1 normal momentum, 2 tangential momentum, 3 energy
   for (int e = tid; e < T::NR * T::WN; e += T::NT) {
     int nl, tl;
-    if (dir == 0) { tl = e / T::WN; nl = e % T::WN; }
-    else { nl = e / T::NR; tl = e % T::NR; }
+    if (dir == 0) {
+      tl = e / T::WN;
+      nl = e % T::WN;
+    } else {
+      nl = e / T::NR;
+      tl = e % T::NR;
+    }
     int n = bc_map(f0 - 3 + nl, Nn, bcn), t = bc_map(t0 - 2 + tl, Nt, bct);
     size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
     sW[0][tl][nl] = W[g];
@@ -143,8 +184,13 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   }
   for (int e = tid; e < T::NR * T::AN; e += T::NT) {
     int nl, tl;
-    if (dir == 0) { tl = e / T::AN; nl = e % T::AN; }
-    else { nl = e / T::NR; tl = e % T::NR; }
+    if (dir == 0) {
+      tl = e / T::AN;
+      nl = e % T::AN;
+    } else {
+      nl = e / T::NR;
+      tl = e % T::NR;
+    }
     int n = bc_map(f0 - 2 + nl, Nn, bcn), t = bc_map(t0 - 2 + tl, Nt, bct);
     size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
     sA[tl][nl] = alpha[g];
@@ -153,8 +199,13 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
 
   // ---- item owned by this thread: interface column fl, segment row rr (row t = t0 - 2 + rr)
   int fl, rr;
-  if (dir == 0) { fl = tid % TF; rr = tid / TF; }
-  else { rr = tid % T::NR; fl = tid / T::NR; }
+  if (dir == 0) {
+    fl = tid % TF;
+    rr = tid / TF;
+  } else {
+    rr = tid % T::NR;
+    fl = tid / T::NR;
+  }
   const int rstride = dir == 0 ? TF : 1;  // thread-index distance between neighbouring rows
   const int f = f0 + fl, t = t0 - 2 + rr;
   const bool live1 = f <= Nn && t < Nt + 2;
@@ -208,18 +259,44 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
 }
 
 // ------------------------------------------------------------------------------------------------
-// Cell kernels.
+// Cell kernels: one thread per cell, 256 cells per workgroup, a workgroup never straddles grids.
+// Cell-block entry (batch form): x = grid, y = first cell of the block.
 // ------------------------------------------------------------------------------------------------
+constexpr int kCellBlock = 256;
+
+struct CellCtx {
+  int gi;
+  size_t o;  // cell index within its grid
+  bool live;
+  GridDesc G;
+};
+
+__device__ __forceinline__ CellCtx cell_ctx(const GridDesc& G0, const GridDesc* grids, const int2* cblocks) {
+  CellCtx c;
+  if (cblocks) {
+    const int2 e = cblocks[blockIdx.x];
+    c.gi = e.x;
+    c.G = grids[e.x];
+    c.o = (size_t)e.y + threadIdx.x;
+  } else {
+    c.gi = 0;
+    c.G = G0;
+    c.o = (size_t)blockIdx.x * kCellBlock + threadIdx.x;
+  }
+  c.live = c.o < (size_t)c.G.nx * c.G.ny;
+  return c;
+}
+
 template <class real>
-__device__ __forceinline__ void face_sum(const real* FX, const real* FY, const KParams& P, int i, int j, int base,
+__device__ __forceinline__ void face_sum(const real* FX, const real* FY, const GridDesc& G, int i, int j, int base,
                                          real* out) {
   // no contraction here: the x and y contributions are rounded alike, so a transposed grid
   // (x <-> y, U <-> V) gives a bitwise transposed result
 #pragma clang fp contract(off)
-  const int nx = P.nx, ny = P.ny;
+  const int nx = G.nx, ny = G.ny;
   const size_t sx = (size_t)ny * (nx + 1), sy = (size_t)(ny + 1) * nx;
   const size_t w = (size_t)j * (nx + 1) + i, s = (size_t)j * nx + i;
-  const real ix = real(P.inv_dx), iy = real(P.inv_dy);
+  const real ix = real(G.inv_dx), iy = real(G.inv_dy);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const real* fx = FX + (base + c) * sx;
@@ -231,17 +308,24 @@ __device__ __forceinline__ void face_sum(const real* FX, const real* FY, const K
 }
 
 template <class real>
-__global__ __launch_bounds__(256) void k_update1(const real* __restrict__ W, const real* __restrict__ FX,
-                                                 const real* __restrict__ FY, real* __restrict__ Ws,
-                                                 real* __restrict__ R, Ctrl* __restrict__ ctrl, KParams P) {
-  if (ctrl->status) return;
-  const size_t N = (size_t)P.nx * P.ny, o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= N) return;
-  const int i = (int)(o % P.nx), j = (int)(o / P.nx);
+__global__ __launch_bounds__(kCellBlock) void k_update1(const real* __restrict__ Wall, const real* __restrict__ FXall,
+                                                        const real* __restrict__ FYall, real* __restrict__ Wsall,
+                                                        real* __restrict__ Rall, Ctrl* __restrict__ ctrls, GridDesc G0,
+                                                        const GridDesc* __restrict__ grids,
+                                                        const int2* __restrict__ cblocks) {
+  const CellCtx C = cell_ctx(G0, grids, cblocks);
+  Ctrl* ctrl = ctrls + C.gi;
+  if (ctrl->status || !C.live) return;
+  const GridDesc& G = C.G;
+  const size_t N = (size_t)G.nx * G.ny, o = C.o;
+  const int i = (int)(o % G.nx), j = (int)(o / G.nx);
+  const real* W = Wall + G.w_off;
+  real* Ws = Wsall + G.w_off;
+  real* R = Rall + G.w_off;
   const real dt = real(ctrl->dt);
   real L[4], Lt[4];
-  face_sum(FX, FY, P, i, j, 0, L);
-  face_sum(FX, FY, P, i, j, 4, Lt);
+  face_sum(FXall + G.fx_off, FYall + G.fy_off, G, i, j, 0, L);
+  face_sum(FXall + G.fx_off, FYall + G.fy_off, G, i, j, 4, Lt);
   const real h1 = real(0.5) * dt, h2 = dt * dt * real(0.125), r2 = dt * dt * real(1.0 / 6.0);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -252,22 +336,22 @@ __global__ __launch_bounds__(256) void k_update1(const real* __restrict__ W, con
 }
 
 template <class real>
-__device__ __forceinline__ bool cell_speed(const real* w, const KParams& P, double& s) {
-  const real g = real(P.gamma);
+__device__ __forceinline__ bool cell_speed(const real* w, const Scheme& S, const GridDesc& G, double& s) {
+  const real g = real(S.gamma);
   real ir = real(1) / w[0];
   real u = w[1] * ir, v = w[2] * ir;
-  real p = real(P.gamma - 1.0) * (w[3] - real(0.5) * (w[1] * u + w[2] * v));
+  real p = real(S.gamma - 1.0) * (w[3] - real(0.5) * (w[1] * u + w[2] * v));
   bool ok = w[0] > real(0) && p > real(0) && isfinite(w[1]) && isfinite(w[2]) && isfinite(w[3]) && isfinite(p);
   real c = sqrt(g * p * ir);
-  real sx = (fabs(u) + c) * real(P.inv_dx), sy = (fabs(v) + c) * real(P.inv_dy);
+  real sx = (fabs(u) + c) * real(G.inv_dx), sy = (fabs(v) + c) * real(G.inv_dy);
   s = ok ? double(sx > sy ? sx : sy) : 0.0;
   return ok;
 }
 
 // Workgroup max of a non-negative double and OR of a flag, then one atomic each.
 __device__ __forceinline__ void block_reduce_commit(double s, int bad, Ctrl* ctrl, int slot, int step_done) {
-  __shared__ double red[16];
-  __shared__ int redb[16];
+  __shared__ double red[kCellBlock / 64];
+  __shared__ int redb[kCellBlock / 64];
   for (int off = 32; off > 0; off >>= 1) {
     double o = __shfl_xor(s, off);
     s = o > s ? o : s;
@@ -292,75 +376,91 @@ __device__ __forceinline__ void block_reduce_commit(double s, int bad, Ctrl* ctr
 }
 
 template <class real>
-__global__ __launch_bounds__(256) void k_update2(real* __restrict__ W, real* __restrict__ alpha,
-                                                 const real* __restrict__ R, const real* __restrict__ FX,
-                                                 const real* __restrict__ FY, Ctrl* __restrict__ ctrl, KParams P,
-                                                 int step) {
-  if (ctrl->status) return;
-  const size_t N = (size_t)P.nx * P.ny, o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kCellBlock) void k_update2(real* __restrict__ Wall, real* __restrict__ Aall,
+                                                        const real* __restrict__ Rall, const real* __restrict__ FXall,
+                                                        const real* __restrict__ FYall, Ctrl* __restrict__ ctrls,
+                                                        GridDesc G0, const GridDesc* __restrict__ grids,
+                                                        const int2* __restrict__ cblocks, Scheme S, int step) {
+  const CellCtx C = cell_ctx(G0, grids, cblocks);
+  Ctrl* ctrl = ctrls + C.gi;
+  if (ctrl->status) return;  // uniform over the workgroup: one grid per workgroup
+  const GridDesc& G = C.G;
   double s = 0.0;
   int bad = 0;
-  if (o < N) {
-    const int i = (int)(o % P.nx), j = (int)(o / P.nx);
+  if (C.live) {
+    const size_t N = (size_t)G.nx * G.ny, o = C.o;
+    const int i = (int)(o % G.nx), j = (int)(o / G.nx);
+    const real* FX = FXall + G.fx_off;
+    const real* FY = FYall + G.fy_off;
+    real* W = Wall + G.w_off;
+    const real* R = Rall + G.w_off;
     const real dt = real(ctrl->dt);
     real Lt[4], w[4];
-    face_sum(FX, FY, P, i, j, 4, Lt);
+    face_sum(FX, FY, G, i, j, 4, Lt);
     const real r3 = dt * dt * real(1.0 / 3.0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       w[c] = R[c * N + o] + r3 * Lt[c];
       W[c * N + o] = w[c];
     }
-    const int nx = P.nx, ny = P.ny;
+    const int nx = G.nx, ny = G.ny;
     const size_t sx = (size_t)ny * (nx + 1), sy = (size_t)(ny + 1) * nx;
     const size_t fw = (size_t)j * (nx + 1) + i;
     const real* ax = FX + 8 * sx;
     const real* ay = FY + 8 * sy;
-    alpha[o] = (ax[fw] * ax[fw + 1]) * (ay[o] * ay[o + nx]);
-    bad = cell_speed(w, P, s) ? 0 : 1;
+    Aall[G.a_off + o] = (ax[fw] * ax[fw + 1]) * (ay[o] * ay[o + nx]);
+    bad = cell_speed(w, S, G, s) ? 0 : 1;
   }
   block_reduce_commit(s, bad, ctrl, (step + 1) & 1, step + 1);
 }
 
 template <class real>
-__global__ __launch_bounds__(256) void k_speed(const real* __restrict__ W, Ctrl* __restrict__ ctrl, KParams P,
-                                               int slot) {
-  const size_t N = (size_t)P.nx * P.ny, o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kCellBlock) void k_speed(const real* __restrict__ Wall, Ctrl* __restrict__ ctrls,
+                                                      GridDesc G0, const GridDesc* __restrict__ grids,
+                                                      const int2* __restrict__ cblocks, Scheme S, int slot) {
+  const CellCtx C = cell_ctx(G0, grids, cblocks);
+  Ctrl* ctrl = ctrls + C.gi;
+  const GridDesc& G = C.G;
   double s = 0.0;
   int bad = 0;
-  if (o < N) {
+  if (C.live) {
+    const size_t N = (size_t)G.nx * G.ny, o = C.o;
+    const real* W = Wall + G.w_off;
     real w[4] = {W[o], W[N + o], W[2 * N + o], W[3 * N + o]};
-    bad = cell_speed(w, P, s) ? 0 : 1;
+    bad = cell_speed(w, S, G, s) ? 0 : 1;
   }
   block_reduce_commit(s, bad, ctrl, slot, 0);
 }
 
-__global__ void k_ctrl_init(Ctrl* ctrl) {
-  ctrl->smax_bits[0] = 0ull;
-  ctrl->smax_bits[1] = 0ull;
-  ctrl->dt = 0.0;
-  ctrl->t = 0.0;
-  ctrl->status = 0;
-  ctrl->fail_step = -1;
+__global__ void k_ctrl_init(Ctrl* ctrls, int n) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  Ctrl* c = ctrls + g;
+  c->smax_bits[0] = 0ull;
+  c->smax_bits[1] = 0ull;
+  c->dt = 0.0;
+  c->t = 0.0;
+  c->status = 0;
+  c->fail_step = -1;
 }
 
 template <class real>
-__global__ __launch_bounds__(256) void k_assemble(const real* __restrict__ FX, const real* __restrict__ FY,
-                                                  real* __restrict__ L, real* __restrict__ Lt,
-                                                  real* __restrict__ an, KParams P) {
-  const size_t N = (size_t)P.nx * P.ny, o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kCellBlock) void k_assemble(const real* __restrict__ FX, const real* __restrict__ FY,
+                                                         real* __restrict__ L, real* __restrict__ Lt,
+                                                         real* __restrict__ an, GridDesc G) {
+  const size_t N = (size_t)G.nx * G.ny, o = (size_t)blockIdx.x * kCellBlock + threadIdx.x;
   if (o >= N) return;
-  const int i = (int)(o % P.nx), j = (int)(o / P.nx);
+  const int i = (int)(o % G.nx), j = (int)(o / G.nx);
   real a[4], b[4];
-  face_sum(FX, FY, P, i, j, 0, a);
-  face_sum(FX, FY, P, i, j, 4, b);
+  face_sum(FX, FY, G, i, j, 0, a);
+  face_sum(FX, FY, G, i, j, 4, b);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     L[c * N + o] = a[c];
     Lt[c * N + o] = b[c];
   }
   if (an) {
-    const int nx = P.nx, ny = P.ny;
+    const int nx = G.nx, ny = G.ny;
     const size_t sx = (size_t)ny * (nx + 1), sy = (size_t)(ny + 1) * nx;
     const size_t fw = (size_t)j * (nx + 1) + i;
     an[o] = (FX[8 * sx + fw] * FX[8 * sx + fw + 1]) * (FY[8 * sy + o] * FY[8 * sy + o + nx]);
@@ -370,8 +470,6 @@ __global__ __launch_bounds__(256) void k_assemble(const real* __restrict__ FX, c
 // ------------------------------------------------------------------------------------------------
 // Host side.
 // ------------------------------------------------------------------------------------------------
-constexpr int kTF = 16, kTR = 28;
-
 static thread_local std::string g_err;
 
 static dfw_status fail(dfw_status s, const std::string& msg) {
@@ -415,6 +513,61 @@ static void timed(int kind, hipStream_t st, Launch launch) {
   if (a && b) g_prof.recs.push_back({kind, a, b});
 }
 
+// Interface tile shapes (TF interfaces x TR segments); index 0 is the library default.
+struct TileShape {
+  int tf, tr;
+};
+static const TileShape kShapes[] = {{16, 28}, {8, 60}, {32, 12}, {16, 12}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+static int shape_tiles(int shape, int nx, int ny) {
+  const TileShape s = kShapes[shape];
+  return ((nx + 1 + s.tf - 1) / s.tf) * ((ny + s.tr - 1) / s.tr) + ((ny + 1 + s.tf - 1) / s.tf) * ((nx + s.tr - 1) / s.tr);
+}
+
+struct FaceLaunch {
+  int shape, flux, out;
+  int nblocks;
+  const int4* tiles;
+  const GridDesc* grids;
+  GridDesc G0;
+  Ctrl* ctrls;
+  Scheme S;
+  double dt_host;
+  int lead, step, nsteps;
+  double* dt_hist;
+};
+
+template <class real, int FLUX, int OUT, int TF, int TR>
+static void launch_faces_t(const FaceLaunch& L, const real* W, const real* A, real* FX, real* FY, hipStream_t st) {
+  hipLaunchKernelGGL((k_faces<real, FLUX, OUT, TF, TR>), dim3(L.nblocks), dim3(TF * (TR + 4)), 0, st, W, A, FX, FY,
+                     L.ctrls, L.G0, L.grids, L.tiles, L.S, L.dt_host, L.lead, L.step, L.nsteps, L.dt_hist);
+}
+
+template <class real, int FLUX, int OUT>
+static void launch_faces_shape(const FaceLaunch& L, const real* W, const real* A, real* FX, real* FY, hipStream_t st) {
+  switch (L.shape) {
+    case 1: launch_faces_t<real, FLUX, OUT, 8, 60>(L, W, A, FX, FY, st); break;
+    case 2: launch_faces_t<real, FLUX, OUT, 32, 12>(L, W, A, FX, FY, st); break;
+    case 3: launch_faces_t<real, FLUX, OUT, 16, 12>(L, W, A, FX, FY, st); break;
+    default: launch_faces_t<real, FLUX, OUT, 16, 28>(L, W, A, FX, FY, st); break;
+  }
+}
+
+template <class real, int OUT>
+static void launch_faces_out(const FaceLaunch& L, const real* W, const real* A, real* FX, real* FY, hipStream_t st) {
+  if (L.flux == DFW_FLUX_LF) launch_faces_shape<real, DFW_FLUX_LF, OUT>(L, W, A, FX, FY, st);
+  else launch_faces_shape<real, DFW_FLUX_GKS, OUT>(L, W, A, FX, FY, st);
+}
+
+template <class real>
+static void launch_faces(const FaceLaunch& L, const real* W, const real* A, real* FX, real* FY, hipStream_t st) {
+  if (L.out == (OUT_F | OUT_FT)) launch_faces_out<real, OUT_F | OUT_FT>(L, W, A, FX, FY, st);
+  else if (L.out == (OUT_FT | OUT_DF)) launch_faces_out<real, OUT_FT | OUT_DF>(L, W, A, FX, FY, st);
+  else launch_faces_out<real, OUT_F | OUT_FT | OUT_DF>(L, W, A, FX, FY, st);
+}
+
+// Workspace of a single grid.
 struct WsLayout {
   size_t ws_off, r_off, fx_off, fy_off, ctrl_off, total;
 };
@@ -437,102 +590,127 @@ static WsLayout layout(const dfw_grid* g, size_t es) {
   return L;
 }
 
-static dfw_status check_common(const dfw_grid* g, const dfw_params* p, int32_t dtype) {
-  if (!g || !p) return fail(DFW_EINVAL, "null grid or params");
+static dfw_status check_grid(const dfw_grid* g) {
+  if (!g) return fail(DFW_EINVAL, "null grid");
   if (g->nx < 1 || g->ny < 1) return fail(DFW_EINVAL, "nx and ny must be >= 1");
   if ((size_t)g->nx * g->ny > ((size_t)1 << 31)) return fail(DFW_EINVAL, "grid too large (nx*ny > 2^31)");
   if (!(g->dx > 0) || !(g->dy > 0)) return fail(DFW_EINVAL, "dx and dy must be > 0");
   if ((g->bc_x != DFW_BC_PERIODIC && g->bc_x != DFW_BC_TRANSMISSIVE) ||
       (g->bc_y != DFW_BC_PERIODIC && g->bc_y != DFW_BC_TRANSMISSIVE))
     return fail(DFW_EINVAL, "unknown boundary condition");
+  return DFW_OK;
+}
+
+static dfw_status check_params(const dfw_params* p, int32_t dtype) {
+  if (!p) return fail(DFW_EINVAL, "null params");
   if (!(p->gamma > 1.0)) return fail(DFW_EINVAL, "gamma must be > 1");
   if (p->flux != DFW_FLUX_LF && p->flux != DFW_FLUX_GKS) return fail(DFW_EINVAL, "unknown flux");
   if (!(p->d_h > 0 && p->d_h < 1) || !(p->d_l >= 0 && p->d_l <= 1)) return fail(DFW_EINVAL, "d_h in (0,1), d_l in [0,1]");
   if (!(p->eps_weno > 0)) return fail(DFW_EINVAL, "eps_weno must be > 0");
   if (!(p->c1 >= 0) || !(p->c2 >= 0)) return fail(DFW_EINVAL, "c1, c2 must be >= 0");
-  if (p->reserved != 0) return fail(DFW_EINVAL, "reserved must be 0");
+  if (p->tile < 0 || p->tile >= kNumShapes) return fail(DFW_EINVAL, "tile must be in [0, dfw_num_tiles())");
   if (dtype != DFW_F64 && dtype != DFW_F32) return fail(DFW_EDTYPE, "dtype must be DFW_F64 or DFW_F32");
   return DFW_OK;
 }
 
-static KParams make_kparams(const dfw_grid* g, const dfw_params* p) {
-  KParams P;
-  P.nx = g->nx;
-  P.ny = g->ny;
-  P.bc_x = g->bc_x;
-  P.bc_y = g->bc_y;
-  P.dx = g->dx;
-  P.dy = g->dy;
-  P.inv_dx = 1.0 / g->dx;
-  P.inv_dy = 1.0 / g->dy;
-  P.gamma = p->gamma;
-  P.cfl = p->cfl;
-  P.dt_fixed = p->dt_fixed;
-  P.alpha_thres = p->alpha_thres;
-  P.eps = p->eps_weno;
-  P.c1 = p->c1;
-  P.c2 = p->c2;
-  P.K = (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0);
-  P.d[3] = p->d_h;
-  P.d[0] = (1.0 - p->d_h) * (1.0 - p->d_l) / 2.0;
-  P.d[1] = (1.0 - p->d_h) * p->d_l;
-  P.d[2] = P.d[0];
-  return P;
+static dfw_status check_common(const dfw_grid* g, const dfw_params* p, int32_t dtype) {
+  dfw_status s = check_grid(g);
+  return s != DFW_OK ? s : check_params(p, dtype);
 }
 
-#define HIP_TRY(x)                                                                          \
-  do {                                                                                      \
-    hipError_t e_ = (x);                                                                    \
+static Scheme make_scheme(const dfw_params* p) {
+  Scheme S;
+  S.gamma = p->gamma;
+  S.cfl = p->cfl;
+  S.dt_fixed = p->dt_fixed;
+  S.alpha_thres = p->alpha_thres;
+  S.eps = p->eps_weno;
+  S.c1 = p->c1;
+  S.c2 = p->c2;
+  S.K = (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0);
+  S.d[3] = p->d_h;
+  S.d[0] = (1.0 - p->d_h) * (1.0 - p->d_l) / 2.0;
+  S.d[1] = (1.0 - p->d_h) * p->d_l;
+  S.d[2] = S.d[0];
+  return S;
+}
+
+static GridDesc make_desc(const dfw_grid* g) {
+  GridDesc G;
+  G.nx = g->nx;
+  G.ny = g->ny;
+  G.bc_x = g->bc_x;
+  G.bc_y = g->bc_y;
+  G.dx = g->dx;
+  G.dy = g->dy;
+  G.inv_dx = 1.0 / g->dx;
+  G.inv_dy = 1.0 / g->dy;
+  G.w_off = G.a_off = G.fx_off = G.fy_off = 0;
+  return G;
+}
+
+#define HIP_TRY(x)                                                                               \
+  do {                                                                                           \
+    hipError_t e_ = (x);                                                                         \
     if (e_ != hipSuccess) return fail(DFW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-template <class real, int FLUX, int OUT>
-static void launch_faces(const real* W, const real* A, real* FX, real* FY, Ctrl* ctrl, const KParams& P,
-                         double dt_host, int lead, int step, double* dt_hist, hipStream_t st) {
-  using T = Tile<kTF, kTR>;
-  int nbx = ((P.nx + 1 + kTF - 1) / kTF) * ((P.ny + kTR - 1) / kTR);
-  int nby = ((P.ny + 1 + kTF - 1) / kTF) * ((P.nx + kTR - 1) / kTR);
-  hipLaunchKernelGGL((k_faces<real, FLUX, OUT, kTF, kTR>), dim3(nbx + nby), dim3(T::NT), 0, st, W, A, FX, FY,
-                     ctrl, P, dt_host, lead, step, dt_hist);
-}
+static unsigned cell_blocks(const GridDesc& G) { return (unsigned)(((size_t)G.nx * G.ny + kCellBlock - 1) / kCellBlock); }
 
-template <class real, int OUT>
-static void launch_faces_flux(int flux, const real* W, const real* A, real* FX, real* FY, Ctrl* ctrl,
-                              const KParams& P, double dt_host, int lead, int step, double* dt_hist,
-                              hipStream_t st) {
-  if (flux == DFW_FLUX_LF) launch_faces<real, DFW_FLUX_LF, OUT>(W, A, FX, FY, ctrl, P, dt_host, lead, step, dt_hist, st);
-  else launch_faces<real, DFW_FLUX_GKS, OUT>(W, A, FX, FY, ctrl, P, dt_host, lead, step, dt_hist, st);
+// The kernels of nsteps S2O4 steps on `st` (no synchronisation).  Single grid: grids/tiles/cblocks
+// are null and G0 describes the grid; batch: the tables describe every grid.
+template <class real>
+static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* FY, Ctrl* ctrls, int nctrl,
+                          const GridDesc& G0, const GridDesc* grids, const int4* tiles, int ntiles,
+                          const int2* cblocks, int ncblocks, const dfw_params* p, int nsteps, double* dt_hist,
+                          hipStream_t st) {
+  const Scheme S = make_scheme(p);
+  FaceLaunch L;
+  L.shape = p->tile;
+  L.flux = p->flux;
+  L.nblocks = ntiles;
+  L.tiles = tiles;
+  L.grids = grids;
+  L.G0 = G0;
+  L.ctrls = ctrls;
+  L.S = S;
+  L.dt_host = p->dt_fixed > 0 ? p->dt_fixed : 0.0;
+  L.nsteps = nsteps;
+  const unsigned nb = (unsigned)ncblocks;
+  hipLaunchKernelGGL(k_ctrl_init, dim3((nctrl + 63) / 64), dim3(64), 0, st, ctrls, nctrl);
+  timed(DFW_K_SPEED, st, [&] {
+    hipLaunchKernelGGL(k_speed<real>, dim3(nb), dim3(kCellBlock), 0, st, W, ctrls, G0, grids, cblocks, S, 0);
+  });
+  for (int n = 0; n < nsteps; ++n) {
+    L.step = n;
+    L.out = OUT_F | OUT_FT;
+    L.lead = 1;
+    L.dt_hist = dt_hist;
+    timed(DFW_K_FACES1, st, [&] { launch_faces<real>(L, W, A, FX, FY, st); });
+    timed(DFW_K_UPDATE1, st, [&] {
+      hipLaunchKernelGGL(k_update1<real>, dim3(nb), dim3(kCellBlock), 0, st, W, FX, FY, Ws, R, ctrls, G0, grids,
+                         cblocks);
+    });
+    L.out = OUT_FT | OUT_DF;
+    L.lead = 0;
+    L.dt_hist = nullptr;
+    timed(DFW_K_FACES2, st, [&] { launch_faces<real>(L, Ws, A, FX, FY, st); });
+    timed(DFW_K_UPDATE2, st, [&] {
+      hipLaunchKernelGGL(k_update2<real>, dim3(nb), dim3(kCellBlock), 0, st, W, A, R, FX, FY, ctrls, G0, grids,
+                         cblocks, S, n);
+    });
+  }
 }
-
-static dim3 cell_grid(const KParams& P) { return dim3((unsigned)(((size_t)P.nx * P.ny + 255) / 256)); }
 
 template <class real>
 static dfw_status run_impl(real* W, real* A, const dfw_grid* g, const dfw_params* p, int nsteps, char* ws,
                            double* dt_hist, double* t_out, int32_t* fail_step, hipStream_t st) {
   WsLayout L = layout(g, sizeof(real));
-  real* Ws = (real*)(ws + L.ws_off);
-  real* R = (real*)(ws + L.r_off);
-  real* FX = (real*)(ws + L.fx_off);
-  real* FY = (real*)(ws + L.fy_off);
   Ctrl* ctrl = (Ctrl*)(ws + L.ctrl_off);
-  KParams P = make_kparams(g, p);
-  const double dth = p->dt_fixed > 0 ? p->dt_fixed : 0.0;
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, st, ctrl);
-  timed(DFW_K_SPEED, st, [&] { hipLaunchKernelGGL(k_speed<real>, cell_grid(P), dim3(256), 0, st, W, ctrl, P, 0); });
-  for (int n = 0; n < nsteps; ++n) {
-    timed(DFW_K_FACES1, st, [&] {
-      launch_faces_flux<real, OUT_F | OUT_FT>(p->flux, W, A, FX, FY, ctrl, P, dth, 1, n, dt_hist, st);
-    });
-    timed(DFW_K_UPDATE1, st, [&] {
-      hipLaunchKernelGGL(k_update1<real>, cell_grid(P), dim3(256), 0, st, W, FX, FY, Ws, R, ctrl, P);
-    });
-    timed(DFW_K_FACES2, st, [&] {
-      launch_faces_flux<real, OUT_FT | OUT_DF>(p->flux, Ws, A, FX, FY, ctrl, P, dth, 0, n, nullptr, st);
-    });
-    timed(DFW_K_UPDATE2, st, [&] {
-      hipLaunchKernelGGL(k_update2<real>, cell_grid(P), dim3(256), 0, st, W, A, R, FX, FY, ctrl, P, n);
-    });
-  }
+  const GridDesc G = make_desc(g);
+  enqueue_steps<real>(W, A, (real*)(ws + L.ws_off), (real*)(ws + L.r_off), (real*)(ws + L.fx_off),
+                      (real*)(ws + L.fy_off), ctrl, 1, G, nullptr, nullptr, shape_tiles(p->tile, g->nx, g->ny),
+                      nullptr, (int)cell_blocks(G), p, nsteps, dt_hist, st);
   HIP_TRY(hipGetLastError());
   Ctrl h;
   HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
@@ -541,6 +719,82 @@ static dfw_status run_impl(real* W, real* A, const dfw_grid* g, const dfw_params
   if (fail_step) *fail_step = h.status ? h.fail_step : -1;
   if (h.status) return fail(DFW_ENONPHYS, "non-physical state after " + std::to_string(h.fail_step) + " steps");
   return DFW_OK;
+}
+
+}  // namespace dfw
+
+// ================================================================================================
+// Batched ragged grids.
+// ================================================================================================
+struct dfw_batch {
+  int ngrids = 0;
+  int32_t dtype = DFW_F64;
+  dfw_params params{};
+  std::vector<dfw::GridDesc> grids;
+  std::vector<int4> tiles;
+  std::vector<int2> cblocks;
+  size_t w_elems = 0, a_elems = 0, fx_elems = 0, fy_elems = 0;
+  size_t ws_off = 0, r_off = 0, fx_off = 0, fy_off = 0, ctrl_off = 0, ws_bytes = 0;
+  void* dtab = nullptr;  // device copy of grids | tiles | cblocks (owned by the plan)
+  dfw::GridDesc* d_grids = nullptr;
+  int4* d_tiles = nullptr;
+  int2* d_cblocks = nullptr;
+  // captured rollout
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  void *g_W = nullptr, *g_A = nullptr, *g_ws = nullptr, *g_dth = nullptr;
+  int g_nsteps = -1;
+};
+
+namespace dfw {
+
+static void build_tiles(dfw_batch* b, int order) {
+  const TileShape s = kShapes[b->params.tile];
+  std::vector<int> idx(b->ngrids);
+  for (int g = 0; g < b->ngrids; ++g) idx[g] = g;
+  if (order == DFW_ORDER_LARGEST_FIRST)
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+      return (long long)b->grids[a].nx * b->grids[a].ny > (long long)b->grids[c].nx * b->grids[c].ny;
+    });
+  b->tiles.clear();
+  std::vector<std::vector<int4>> per_grid(b->ngrids);
+  for (int g : idx) {
+    const GridDesc& G = b->grids[g];
+    bool first = true;
+    for (int dir = 0; dir < 2; ++dir) {
+      const int Nn = dir ? G.ny : G.nx, Nt = dir ? G.nx : G.ny;
+      for (int t0 = 0; t0 < Nt; t0 += s.tr)
+        for (int f0 = 0; f0 <= Nn; f0 += s.tf) {
+          per_grid[g].push_back(make_int4(g, dir | (first ? 2 : 0), f0, t0));
+          first = false;
+        }
+    }
+  }
+  if (order == DFW_ORDER_INTERLEAVED) {  // round-robin over grids: neighbouring workgroups differ in grid
+    size_t longest = 0;
+    for (int g : idx) longest = std::max(longest, per_grid[g].size());
+    for (size_t k = 0; k < longest; ++k)
+      for (int g : idx)
+        if (k < per_grid[g].size()) b->tiles.push_back(per_grid[g][k]);
+  } else {
+    for (int g : idx) b->tiles.insert(b->tiles.end(), per_grid[g].begin(), per_grid[g].end());
+  }
+}
+
+template <class real>
+static void batch_enqueue(dfw_batch* b, void* W, void* A, char* ws, int nsteps, double* dth, hipStream_t st) {
+  enqueue_steps<real>((real*)W, (real*)A, (real*)(ws + b->ws_off), (real*)(ws + b->r_off), (real*)(ws + b->fx_off),
+                      (real*)(ws + b->fy_off), (Ctrl*)(ws + b->ctrl_off), b->ngrids, b->grids[0], b->d_grids,
+                      b->d_tiles, (int)b->tiles.size(), b->d_cblocks, (int)b->cblocks.size(), &b->params, nsteps, dth,
+                      st);
+}
+
+static void drop_graph(dfw_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
 }
 
 }  // namespace dfw
@@ -575,8 +829,8 @@ dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params*
   if (dtype == DFW_F64)
     return run_impl<double>((double*)W, (double*)alpha, grid, params, nsteps, (char*)ws, dt_hist_dev, t_out,
                             fail_step, st);
-  return run_impl<float>((float*)W, (float*)alpha, grid, params, nsteps, (char*)ws, dt_hist_dev, t_out,
-                         fail_step, st);
+  return run_impl<float>((float*)W, (float*)alpha, grid, params, nsteps, (char*)ws, dt_hist_dev, t_out, fail_step,
+                         st);
 }
 
 dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* params, int32_t dtype, void* ws,
@@ -588,10 +842,15 @@ dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* 
   hipStream_t st = (hipStream_t)stream;
   WsLayout L = layout(grid, dtype == DFW_F32 ? 4 : 8);
   Ctrl* ctrl = (Ctrl*)((char*)ws + L.ctrl_off);
-  KParams P = make_kparams(grid, params);
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, st, ctrl);
-  if (dtype == DFW_F64) hipLaunchKernelGGL(k_speed<double>, cell_grid(P), dim3(256), 0, st, (const double*)W, ctrl, P, 0);
-  else hipLaunchKernelGGL(k_speed<float>, cell_grid(P), dim3(256), 0, st, (const float*)W, ctrl, P, 0);
+  const GridDesc G = make_desc(grid);
+  const Scheme S = make_scheme(params);
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, 1);
+  if (dtype == DFW_F64)
+    hipLaunchKernelGGL(k_speed<double>, dim3(cell_blocks(G)), dim3(kCellBlock), 0, st, (const double*)W, ctrl, G,
+                       nullptr, nullptr, S, 0);
+  else
+    hipLaunchKernelGGL(k_speed<float>, dim3(cell_blocks(G)), dim3(kCellBlock), 0, st, (const float*)W, ctrl, G,
+                       nullptr, nullptr, S, 0);
   HIP_TRY(hipGetLastError());
   Ctrl h;
   HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
@@ -613,26 +872,192 @@ dfw_status dfw_rhs(const void* W, const void* alpha, const dfw_grid* grid, const
   hipStream_t st = (hipStream_t)stream;
   WsLayout Lw = layout(grid, dtype == DFW_F32 ? 4 : 8);
   Ctrl* ctrl = (Ctrl*)((char*)ws + Lw.ctrl_off);
-  KParams P = make_kparams(grid, params);
-  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, st, ctrl);
+  const GridDesc G = make_desc(grid);
+  FaceLaunch FL;
+  FL.shape = params->tile;
+  FL.flux = params->flux;
+  FL.out = OUT_F | OUT_FT | OUT_DF;
+  FL.nblocks = shape_tiles(params->tile, grid->nx, grid->ny);
+  FL.tiles = nullptr;
+  FL.grids = nullptr;
+  FL.G0 = G;
+  FL.ctrls = ctrl;
+  FL.S = make_scheme(params);
+  FL.dt_host = dt;
+  FL.lead = 0;
+  FL.step = 0;
+  FL.nsteps = 1;
+  FL.dt_hist = nullptr;
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, 1);
   if (dtype == DFW_F64) {
     double* FX = (double*)((char*)ws + Lw.fx_off);
     double* FY = (double*)((char*)ws + Lw.fy_off);
-    launch_faces_flux<double, OUT_F | OUT_FT | OUT_DF>(params->flux, (const double*)W, (const double*)alpha, FX, FY,
-                                                       ctrl, P, dt, 0, 0, nullptr, st);
-    hipLaunchKernelGGL(k_assemble<double>, cell_grid(P), dim3(256), 0, st, FX, FY, (double*)L, (double*)Lt,
-                       (double*)alpha_new, P);
+    launch_faces<double>(FL, (const double*)W, (const double*)alpha, FX, FY, st);
+    hipLaunchKernelGGL(k_assemble<double>, dim3(cell_blocks(G)), dim3(kCellBlock), 0, st, FX, FY, (double*)L,
+                       (double*)Lt, (double*)alpha_new, G);
   } else {
     float* FX = (float*)((char*)ws + Lw.fx_off);
     float* FY = (float*)((char*)ws + Lw.fy_off);
-    launch_faces_flux<float, OUT_F | OUT_FT | OUT_DF>(params->flux, (const float*)W, (const float*)alpha, FX, FY,
-                                                      ctrl, P, dt, 0, 0, nullptr, st);
-    hipLaunchKernelGGL(k_assemble<float>, cell_grid(P), dim3(256), 0, st, FX, FY, (float*)L, (float*)Lt,
-                       (float*)alpha_new, P);
+    launch_faces<float>(FL, (const float*)W, (const float*)alpha, FX, FY, st);
+    hipLaunchKernelGGL(k_assemble<float>, dim3(cell_blocks(G)), dim3(kCellBlock), 0, st, FX, FY, (float*)L,
+                       (float*)Lt, (float*)alpha_new, G);
   }
   HIP_TRY(hipGetLastError());
   return DFW_OK;
 }
+
+// ---- batched ragged grids ----
+
+dfw_status dfw_batch_plan(const dfw_grid* grids, int32_t ngrids, const dfw_params* params, int32_t dtype,
+                          int32_t order, dfw_batch** out) {
+  if (!out) return fail(DFW_EINVAL, "out is null");
+  *out = nullptr;
+  if (!grids || ngrids < 1) return fail(DFW_EINVAL, "need at least one grid");
+  dfw_status s = check_params(params, dtype);
+  if (s != DFW_OK) return s;
+  if (!(params->dt_fixed > 0) && !(params->cfl > 0)) return fail(DFW_EINVAL, "need cfl > 0 or dt_fixed > 0");
+  if (order < 0 || order > DFW_ORDER_INTERLEAVED) return fail(DFW_EINVAL, "unknown sweep order");
+  dfw_batch* b = new dfw_batch();
+  b->ngrids = ngrids;
+  b->dtype = dtype;
+  b->params = *params;
+  const size_t es = dtype == DFW_F32 ? 4 : 8;
+  for (int g = 0; g < ngrids; ++g) {
+    if ((s = check_grid(&grids[g])) != DFW_OK) {
+      delete b;
+      return fail(s, "grid " + std::to_string(g) + ": " + g_err);
+    }
+    GridDesc G = make_desc(&grids[g]);
+    const size_t N = (size_t)G.nx * G.ny;
+    G.w_off = (long long)b->w_elems;
+    G.a_off = (long long)b->a_elems;
+    G.fx_off = (long long)b->fx_elems;
+    G.fy_off = (long long)b->fy_elems;
+    b->w_elems += 4 * N;
+    b->a_elems += N;
+    b->fx_elems += 9 * (size_t)G.ny * (G.nx + 1);
+    b->fy_elems += 9 * (size_t)(G.ny + 1) * G.nx;
+    b->grids.push_back(G);
+    const size_t ncb = (N + kCellBlock - 1) / kCellBlock;
+    for (size_t k = 0; k < ncb; ++k) b->cblocks.push_back(make_int2(g, (int)(k * kCellBlock)));
+  }
+  if (b->w_elems >= ((size_t)1 << 40) || b->tiles.size() > ((size_t)1 << 30)) {
+    delete b;
+    return fail(DFW_EINVAL, "batch too large");
+  }
+  build_tiles(b, order);
+  size_t off = 0;
+  b->ws_off = off;
+  off = align256(off + b->w_elems * es);
+  b->r_off = off;
+  off = align256(off + b->w_elems * es);
+  b->fx_off = off;
+  off = align256(off + b->fx_elems * es);
+  b->fy_off = off;
+  off = align256(off + b->fy_elems * es);
+  b->ctrl_off = off;
+  off = align256(off + (size_t)ngrids * sizeof(Ctrl));
+  b->ws_bytes = off;
+  const size_t tb_g = align256(b->grids.size() * sizeof(GridDesc));
+  const size_t tb_t = align256(b->tiles.size() * sizeof(int4));
+  const size_t tb_c = align256(b->cblocks.size() * sizeof(int2));
+  hipError_t e = hipMalloc(&b->dtab, tb_g + tb_t + tb_c);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(DFW_EHIP, std::string("hipMalloc of the batch tables: ") + hipGetErrorString(e));
+  }
+  b->d_grids = (GridDesc*)b->dtab;
+  b->d_tiles = (int4*)((char*)b->dtab + tb_g);
+  b->d_cblocks = (int2*)((char*)b->dtab + tb_g + tb_t);
+  if (hipMemcpy(b->d_grids, b->grids.data(), b->grids.size() * sizeof(GridDesc), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_cblocks, b->cblocks.data(), b->cblocks.size() * sizeof(int2), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    (void)hipFree(b->dtab);
+    delete b;
+    return fail(DFW_EHIP, "copying the batch tables failed");
+  }
+  *out = b;
+  return DFW_OK;
+}
+
+dfw_status dfw_batch_layout(const dfw_batch* b, int64_t* w_offsets, int64_t* a_offsets, size_t* w_elems,
+                            size_t* a_elems, size_t* ws_bytes) {
+  if (!b) return fail(DFW_EINVAL, "null batch");
+  for (int g = 0; g < b->ngrids; ++g) {
+    if (w_offsets) w_offsets[g] = b->grids[g].w_off;
+    if (a_offsets) a_offsets[g] = b->grids[g].a_off;
+  }
+  if (w_elems) *w_elems = b->w_elems;
+  if (a_elems) *a_elems = b->a_elems;
+  if (ws_bytes) *ws_bytes = b->ws_bytes;
+  return DFW_OK;
+}
+
+dfw_status dfw_batch_run(dfw_batch* b, void* W_flat, void* alpha_flat, int32_t nsteps, void* ws, size_t ws_bytes,
+                         int32_t use_graph, double* dt_hist_dev, double* t_out, int32_t* fail_steps, void* stream) {
+  if (!b) return fail(DFW_EINVAL, "null batch");
+  if (!W_flat || !alpha_flat) return fail(DFW_EINVAL, "W_flat and alpha_flat must be non-null");
+  if (nsteps < 0) return fail(DFW_EINVAL, "nsteps must be >= 0");
+  if (!ws) return fail(DFW_EWORKSPACE, "workspace is null");
+  if (((uintptr_t)ws) & 255) return fail(DFW_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < b->ws_bytes) return fail(DFW_EWORKSPACE, "workspace too small: need " + std::to_string(b->ws_bytes));
+  hipStream_t st = (hipStream_t)stream;
+  if (use_graph) {
+    const bool same = b->exec && b->g_W == W_flat && b->g_A == alpha_flat && b->g_ws == ws &&
+                      b->g_dth == (void*)dt_hist_dev && b->g_nsteps == nsteps;
+    if (!same) {
+      drop_graph(b);
+      if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      const bool prof = g_prof.on;
+      g_prof.on = false;  // no events inside the graph
+      if (b->dtype == DFW_F64) batch_enqueue<double>(b, W_flat, alpha_flat, (char*)ws, nsteps, dt_hist_dev, b->cap_stream);
+      else batch_enqueue<float>(b, W_flat, alpha_flat, (char*)ws, nsteps, dt_hist_dev, b->cap_stream);
+      g_prof.on = prof;
+      hipError_t le = hipGetLastError();
+      hipError_t ce = hipStreamEndCapture(b->cap_stream, &b->graph);
+      if (le != hipSuccess || ce != hipSuccess) {
+        drop_graph(b);
+        return fail(DFW_EHIP, std::string("graph capture failed: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+      }
+      HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->g_W = W_flat;
+      b->g_A = alpha_flat;
+      b->g_ws = ws;
+      b->g_dth = (void*)dt_hist_dev;
+      b->g_nsteps = nsteps;
+    }
+    hipError_t ge = hipSuccess;
+    timed(DFW_K_GRAPH, st, [&] { ge = hipGraphLaunch(b->exec, st); });
+    HIP_TRY(ge);
+  } else {
+    if (b->dtype == DFW_F64) batch_enqueue<double>(b, W_flat, alpha_flat, (char*)ws, nsteps, dt_hist_dev, st);
+    else batch_enqueue<float>(b, W_flat, alpha_flat, (char*)ws, nsteps, dt_hist_dev, st);
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<Ctrl> h(b->ngrids);
+  HIP_TRY(hipMemcpyAsync(h.data(), (char*)ws + b->ctrl_off, b->ngrids * sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int nbad = 0;
+  for (int g = 0; g < b->ngrids; ++g) {
+    if (t_out) t_out[g] = h[g].t;
+    if (fail_steps) fail_steps[g] = h[g].status ? h[g].fail_step : -1;
+    nbad += h[g].status ? 1 : 0;
+  }
+  if (nbad) return fail(DFW_ENONPHYS, std::to_string(nbad) + " grid(s) met a non-physical state");
+  return DFW_OK;
+}
+
+void dfw_batch_free(dfw_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->dtab) (void)hipFree(b->dtab);
+  delete b;
+}
+
+// ---- measurement ----
 
 dfw_status dfw_profile(int32_t enable) {
   g_prof.recs.clear();
@@ -656,6 +1081,15 @@ dfw_status dfw_profile_read(double* ms, int64_t* launches, int32_t n) {
       launches[r.kind] += 1;
     }
   }
+  return DFW_OK;
+}
+
+int32_t dfw_num_tiles(void) { return kNumShapes; }
+
+dfw_status dfw_tile_shape(int32_t tile, int32_t* tf, int32_t* tr) {
+  if (tile < 0 || tile >= kNumShapes) return fail(DFW_EINVAL, "tile out of range");
+  if (tf) *tf = kShapes[tile].tf;
+  if (tr) *tr = kShapes[tile].tr;
   return DFW_OK;
 }
 

@@ -37,12 +37,12 @@ def test_struct_layout_matches_header(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dfweno.h"\nint main(void){'
                    'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dfw_grid), offsetof(dfw_grid, dx),'
                    ' offsetof(dfw_grid, bc_y), sizeof(dfw_params), offsetof(dfw_params, c2),'
-                   ' offsetof(dfw_params, reserved)); return 0;}\n')
+                   ' offsetof(dfw_params, tile)); return 0;}\n')
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(_lib.dfw_grid), _lib.dfw_grid.dx.offset, _lib.dfw_grid.bc_y.offset,
-            ctypes.sizeof(_lib.dfw_params), _lib.dfw_params.c2.offset, _lib.dfw_params.reserved.offset]
+            ctypes.sizeof(_lib.dfw_params), _lib.dfw_params.c2.offset, _lib.dfw_params.tile.offset]
     assert out == want
 
 
@@ -52,7 +52,7 @@ def _grid(nx=8, ny=8):
 
 def _params(**kw):
     d = dict(gamma=1.4, cfl=0.5, dt_fixed=0.0, alpha_thres=0.5, d_h=0.85, d_l=0.85, eps_weno=1e-6, c1=0.01, c2=5.0,
-             flux=0, reserved=0)
+             flux=0, tile=0)
     d.update(kw)
     return _lib.dfw_params(*[d[k] for k, _ in _lib.dfw_params._fields_])
 
@@ -73,7 +73,7 @@ def test_workspace_bytes_host_only():
     (dict(params=_params(gamma=1.0)), _lib.DFW_EINVAL),
     (dict(params=_params(flux=7)), _lib.DFW_EINVAL),
     (dict(params=_params(cfl=0.0, dt_fixed=0.0)), _lib.DFW_EINVAL),
-    (dict(params=_params(reserved=1)), _lib.DFW_EINVAL),
+    (dict(params=_params(tile=99)), _lib.DFW_EINVAL),
     (dict(dtype=5), _lib.DFW_EDTYPE),
     (dict(W=None), _lib.DFW_EINVAL),
     (dict(nsteps=-1), _lib.DFW_EINVAL),

@@ -1,0 +1,177 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+* 512x512 Riemann, GKS, 200 steps (the benchmark workload): the whole run against the oracle's
+  stored result (tests/golden/make_riemann512.py, oracle only) at 4096 seeded cells and the two
+  centre lines, plus the dt history.
+* 4096x4096 circles, LF and GKS, FP64 and FP32: one step at full size against the oracle on
+  sampled patches (the oracle computes dt from the whole grid; each patch carries a 10-cell halo,
+  of which one step contaminates at most 6), five steps with a fixed dt on patches with a 36-cell
+  halo, and the full 50-step run checked by properties that hold at any size (no non-physical
+  state, conservation on the periodic grid, DF in [0, 1])."""
+import functools
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2402_10914_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "riemann512_gks_200.npz")
+
+
+def _api():
+    from paper_2402_10914_amd import api
+    return api
+
+
+def _rel_l1_rows(a, b):
+    return max(float(np.abs(a[c] - b[c]).sum() / np.abs(b[c]).sum()) for c in range(a.shape[0]))
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD), reason="golden file not generated")
+def test_riemann512_gks_200_steps_against_stored_oracle():
+    g = np.load(GOLD)
+    pr = WL.riemann4(512, seed=2402, flux=WL.FLUX_GKS, cfl=0.4, nsteps=200)
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=api.FLUX_GKS, cfl=0.4))
+    W = torch.tensor(pr.W, device="cuda")
+    A = torch.tensor(pr.alpha, device="cuda")
+    dth = torch.zeros(200, dtype=torch.float64, device="cuda")
+    t, fs = st.run(W, A, 200, dt_hist=dth)
+    assert fs == -1
+    Wn = W.cpu().numpy()
+    An = A.cpu().numpy()
+    jj, ii = g["jj"], g["ii"]
+    assert _rel_l1_rows(Wn[:, jj, ii], g["W_s"]) <= 1e-12
+    assert np.abs(An[jj, ii] - g["a_s"]).sum() / np.abs(g["a_s"]).sum() <= 1e-12
+    assert _rel_l1_rows(Wn[:, 256, :], g["W_row"]) <= 1e-12
+    assert _rel_l1_rows(Wn[:, :, 256], g["W_col"]) <= 1e-12
+    np.testing.assert_allclose(dth.cpu().numpy(), g["dt_hist"], rtol=1e-12)
+    assert abs(t - float(g["t"])) <= 1e-12 * float(g["t"])
+    np.testing.assert_allclose(np.abs(Wn).sum(axis=(1, 2)), g["abs_sums"], rtol=1e-12)
+
+
+@functools.lru_cache(maxsize=1)
+def _circles_ic():
+    return WL.circles(4096, seed=10914, cfl=0.4, nsteps=50)
+
+
+def _circles(flux):
+    pr = _circles_ic()
+    pr.flux = flux  # the initial state does not depend on the flux
+    return pr
+
+
+def _patch(A, jc, ic, h):
+    n = A.shape[-1]
+    idx_j = np.arange(jc - h, jc + h + 1) % n
+    idx_i = np.arange(ic - h, ic + h + 1) % n
+    return np.ascontiguousarray(A[..., idx_j[:, None], idx_i[None, :]])
+
+
+def _centres(W0, k_rand=10, k_grad=10, seed=4096):
+    rng = np.random.default_rng(seed)
+    n = W0.shape[-1]
+    p = 0.4 * (W0[3] - 0.5 * (W0[1] ** 2 + W0[2] ** 2) / W0[0])
+    gx = np.abs(np.roll(p, -1, 1) - p)
+    flat = np.argsort(gx.ravel())[::-1]
+    picks = [np.unravel_index(flat[i * 997], gx.shape) for i in range(k_grad)]
+    picks += [tuple(rng.integers(0, n, 2)) for _ in range(k_rand)]
+    return picks
+
+
+def _oracle_patches(W0, A0, dt, flux, steps, halo, centres):
+    n = W0.shape[-1]
+    d = 2.0 / n
+    outs = []
+    for jc, ic in centres:
+        Wp = _patch(W0, jc, ic, halo)
+        Ap = _patch(A0, jc, ic, halo)
+        m = 2 * halo + 1
+        g = O.make_grid(m, m, d, d, O.BC_TRANSMISSIVE)
+        Wr, Ar, _, _, fs = O.run(Wp, Ap, g, O.make_params(flux=flux, cfl=0.4, dt_fixed=dt), steps)
+        assert fs == -1
+        k = halo - 6 * steps
+        outs.append((Wr[:, halo - k:halo + k + 1, halo - k:halo + k + 1], Ar[halo - k:halo + k + 1, halo - k:halo + k + 1]))
+    return outs
+
+
+def _gpu_patches(Wg, Ag, centres, k):
+    outs = []
+    for jc, ic in centres:
+        outs.append((_patch(Wg, jc, ic, k), _patch(Ag, jc, ic, k)))
+    return outs
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+def test_circles4096_one_step_on_patches(flux, dtype):
+    pr = _circles(flux)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, cfl=0.4), tdt)
+    W = torch.tensor(pr.W, dtype=tdt, device="cuda")
+    A = torch.tensor(pr.alpha, dtype=tdt, device="cuda")
+    dth = torch.zeros(1, dtype=torch.float64, device="cuda")
+    _, fs = st.run(W, A, 1, dt_hist=dth)
+    assert fs == -1
+    smax, ok = O.max_speed(pr.W, O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy), O.make_params())
+    dt = 0.4 / smax
+    assert ok
+    assert abs(float(dth[0]) - dt) <= (1e-14 if dtype == "f64" else 1e-6) * dt
+    centres = _centres(pr.W)
+    ref = _oracle_patches(pr.W, pr.alpha, dt, flux, 1, 10, centres)
+    got = _gpu_patches(W.double().cpu().numpy(), A.double().cpu().numpy(), centres, 4)
+    Wr = np.concatenate([r[0].reshape(4, -1) for r in ref], axis=1)
+    Wg = np.concatenate([g[0].reshape(4, -1) for g in got], axis=1)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert _rel_l1_rows(Wg, Wr) <= tol
+    ar = np.concatenate([r[1].ravel() for r in ref])
+    ag = np.concatenate([g[1].ravel() for g in got])
+    assert np.abs(ag - ar).sum() / np.abs(ar).sum() <= (1e-12 if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+def test_circles4096_five_fixed_steps_on_patches(flux):
+    pr = _circles(flux)
+    smax, _ = O.max_speed(pr.W, O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy), O.make_params())
+    dt = 0.4 / smax
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, cfl=0.4, dt_fixed=dt))
+    W = torch.tensor(pr.W, device="cuda")
+    A = torch.tensor(pr.alpha, device="cuda")
+    _, fs = st.run(W, A, 5)
+    assert fs == -1
+    centres = _centres(pr.W, k_rand=4, k_grad=4)
+    ref = _oracle_patches(pr.W, pr.alpha, dt, flux, 5, 36, centres)
+    got = _gpu_patches(W.cpu().numpy(), A.cpu().numpy(), centres, 6)
+    Wr = np.concatenate([r[0].reshape(4, -1) for r in ref], axis=1)
+    Wg = np.concatenate([g[0].reshape(4, -1) for g in got], axis=1)
+    assert _rel_l1_rows(Wg, Wr) <= 1e-12
+    ar = np.concatenate([r[1].ravel() for r in ref])
+    ag = np.concatenate([g[1].ravel() for g in got])
+    assert np.abs(ag - ar).sum() / np.abs(ar).sum() <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+def test_circles4096_fifty_steps_properties(flux, dtype):
+    pr = _circles(flux)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, cfl=0.4), tdt)
+    W = torch.tensor(pr.W, dtype=tdt, device="cuda")
+    A = torch.tensor(pr.alpha, dtype=tdt, device="cuda")
+    s0 = W.double().sum(dim=(1, 2))
+    _, fs = st.run(W, A, 50)
+    assert fs == -1
+    s1 = W.double().sum(dim=(1, 2))
+    scale = W.double().abs().sum(dim=(1, 2))
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert float(((s1 - s0).abs() / scale).max()) <= tol
+    assert float(A.min()) >= 0.0 and float(A.max()) <= 1.0
+    assert float(A.min()) < 0.5  # the blast edges engage the hybrid switch
