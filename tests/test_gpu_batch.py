@@ -65,7 +65,7 @@ def _batched(probs, params, nsteps, dtype=torch.float64, order=0, use_graph=True
 
 def _same(x, y):
     for (w1, a1, t1, f1, d1), (w2, a2, t2, f2, d2) in zip(x, y):
-        assert np.array_equal(w1, w2) and np.array_equal(a1, a2)
+        assert np.array_equal(w1, w2, equal_nan=True) and np.array_equal(a1, a2, equal_nan=True)
         assert t1 == t2 and f1 == f2 and np.array_equal(d1, d2)
 
 
