@@ -125,6 +125,45 @@ dfw_status dfw_batch_run(dfw_batch* b, void* W_flat, void* alpha_flat, int32_t n
 
 void dfw_batch_free(dfw_batch* b);
 
+/* ---- Reverse mode (adjoint) -------------------------------------------------------------------
+ * The gradient of a scalar loss J(W^N, alpha^N) of an N-step rollout (eq. (24) steps, Section 3)
+ * with respect to its initial state (W^0, alpha^0), by the hand-written adjoint of every operation
+ * of the step: characteristic projection, WENO-AO(5,3) with WENO-Z weights and the DF hybrid
+ * (Section 3.1, eqs. (11)-(21) and (34)), the DF factor (Section 3.2), the LF and GKS fluxes and
+ * their time derivatives (Section 2), and the two S2O4 stages.  The time steps are held fixed at a
+ * recorded dt history (the CFL reduction is not differentiated).  Kinks follow one fixed
+ * subgradient convention: d|x|/dx = sign(x) with sign(0) = 0; max(a, b) follows a when a >= b; the
+ * switch of eq. (34) contributes no derivative (the branch taken is differentiated).
+ *
+ * Memory: dfw_run_ckpt stores (W, alpha) at every ckpt_every-th step; dfw_adjoint recomputes one
+ * segment of ckpt_every steps at a time from its checkpoint and reverses it.  The adjoint is FP64
+ * (dtype DFW_F64; DFW_F32 gives DFW_EDTYPE).  Deterministic: no atomics, results are bitwise
+ * reproducible. */
+
+/* Bytes of the checkpoint store of an nsteps rollout (0 for invalid arguments). */
+size_t dfw_checkpoint_bytes(const dfw_grid* grid, int32_t dtype, int32_t nsteps, int32_t ckpt_every);
+
+/* dfw_run (same arguments and results) that also writes checkpoints to ckpt (device, owned by the
+ * caller, >= dfw_checkpoint_bytes, 256-byte aligned).  dt_hist_dev is required here: it records
+ * the time steps the adjoint is taken at. */
+dfw_status dfw_run_ckpt(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
+                        int32_t dtype, int32_t ckpt_every, void* ckpt, size_t ckpt_bytes, void* ws,
+                        size_t ws_bytes, double* dt_hist_dev, double* t_out, int32_t* fail_step, void* stream);
+
+/* Workspace bytes of dfw_adjoint (0 for invalid arguments); about (11 ckpt_every + 70) N values. */
+size_t dfw_adjoint_workspace_bytes(const dfw_grid* grid, int32_t dtype, int32_t ckpt_every);
+
+/* Adjoint of the rollout recorded by dfw_run_ckpt (same grid, params, nsteps, ckpt_every; ckpt and
+ * dt_hist_dev as it wrote them).  In: gW_final = dJ/dW^N ([4][ny][nx]), gA_final = dJ/dalpha^N
+ * ([ny][nx]; NULL means zero).  Out: gW0 = dJ/dW^0, gA0 = dJ/dalpha^0 (NULL: not written).  All
+ * device pointers; the outputs may not alias the inputs or the workspace.  Stream-ordered; waits
+ * for the stream once at the end.  DFW_ENONPHYS if the recomputed forward meets a non-physical
+ * state (a dt_hist other than the recorded one). */
+dfw_status dfw_adjoint(const dfw_grid* grid, const dfw_params* params, int32_t dtype, int32_t nsteps,
+                       int32_t ckpt_every, const void* ckpt, size_t ckpt_bytes, const double* dt_hist_dev,
+                       const void* gW_final, const void* gA_final, void* gW0, void* gA0, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* Interface tile shapes available for dfw_params.tile: TF interfaces by TR segments. */
 int32_t dfw_num_tiles(void);
 dfw_status dfw_tile_shape(int32_t tile, int32_t* tf, int32_t* tr);
@@ -138,7 +177,10 @@ enum {
   DFW_K_UPDATE2 = 3,  /* cell kernel, second stage (W^{n+1}, alpha^{n+1}, CFL reduction) */
   DFW_K_SPEED = 4,    /* standalone CFL reduction of the input state */
   DFW_K_GRAPH = 5,    /* one replay of a captured batched rollout */
-  DFW_K_COUNT = 6
+  DFW_K_ADJ_FACES1 = 6, /* adjoint interface kernel, first stage */
+  DFW_K_ADJ_FACES2 = 7, /* adjoint interface kernel, second stage */
+  DFW_K_ADJ_GATHER = 8, /* adjoint cell gather (both stages) */
+  DFW_K_COUNT = 9
 };
 
 /* enable != 0 clears the records and starts recording; 0 stops.  Process-wide, not thread-safe;

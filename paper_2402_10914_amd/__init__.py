@@ -9,7 +9,8 @@ The C ABI is declared in ``include/dfweno.h``; ``workloads`` builds the seeded s
 Attributes that need torch are imported lazily so that the input generators work without it.
 """
 
-_API = {"Stepper", "Params", "Batch", "KernelProfile", "tile_shapes", "run", "FLUX_LF", "FLUX_GKS", "BC_PERIODIC", "BC_TRANSMISSIVE", "DFWError"}
+_API = {"Stepper", "Params", "Batch", "Adjoint", "Rollout", "rollout", "KernelProfile", "tile_shapes", "run", "FLUX_LF",
+        "FLUX_GKS", "BC_PERIODIC", "BC_TRANSMISSIVE", "DFWError"}
 
 
 def __getattr__(name):

@@ -16,7 +16,8 @@ DFW_OK, DFW_EINVAL, DFW_EDTYPE, DFW_EWORKSPACE, DFW_EHIP, DFW_ENONPHYS = range(6
 DFW_FLUX_LF, DFW_FLUX_GKS = 0, 1
 DFW_BC_PERIODIC, DFW_BC_TRANSMISSIVE = 0, 1
 DFW_F64, DFW_F32 = 0, 1
-KERNEL_KINDS = ["faces1", "update1", "faces2", "update2", "speed", "graph"]
+KERNEL_KINDS = ["faces1", "update1", "faces2", "update2", "speed", "graph", "adj_faces1", "adj_faces2",
+                "adj_gather"]
 DFW_ORDER_GRID, DFW_ORDER_LARGEST_FIRST, DFW_ORDER_INTERLEAVED = 0, 1, 2
 
 
@@ -62,6 +63,12 @@ SIGNATURES = {
     "dfw_batch_run": (ctypes.c_int32, [_VP, _VP, _VP, ctypes.c_int32, _VP, ctypes.c_size_t, ctypes.c_int32, _VP,
                                        _DP, _IP, _VP]),
     "dfw_batch_free": (None, [_VP]),
+    "dfw_checkpoint_bytes": (ctypes.c_size_t, [_GP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "dfw_run_ckpt": (ctypes.c_int32, [_VP, _VP, _GP, _PP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                      ctypes.c_size_t, _VP, ctypes.c_size_t, _VP, _DP, _IP, _VP]),
+    "dfw_adjoint_workspace_bytes": (ctypes.c_size_t, [_GP, ctypes.c_int32, ctypes.c_int32]),
+    "dfw_adjoint": (ctypes.c_int32, [_GP, _PP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t,
+                                     _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "dfw_num_tiles": (ctypes.c_int32, []),
     "dfw_tile_shape": (ctypes.c_int32, [ctypes.c_int32, _IP, _IP]),
     "dfw_profile": (ctypes.c_int32, [ctypes.c_int32]),

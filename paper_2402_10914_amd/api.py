@@ -213,6 +213,95 @@ class Batch:
         return list(t), list(fs)
 
 
+def _aligned_buffer(nbytes: int, device) -> tuple[torch.Tensor, ctypes.c_void_p]:
+    buf = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=device)
+    return buf, ctypes.c_void_p(buf.data_ptr() + (-buf.data_ptr()) % 256)
+
+
+class Adjoint:
+    """Checkpointed rollout of one grid and its hand-written adjoint (FP64).
+
+        adj = Adjoint(stepper, nsteps, ckpt_every=10)
+        t, fail_step = adj.forward(W, alpha)           # in place; records checkpoints and dt
+        gW0, gA0 = adj.backward(gW_N, gA_N)            # dJ/dW^0, dJ/dalpha^0 at the recorded dt
+
+    The time steps are held at the recorded values (the CFL reduction is not differentiated)."""
+
+    def __init__(self, stepper: Stepper, nsteps: int, ckpt_every: int = 10):
+        if stepper.dtype != torch.float64:
+            raise TypeError("the adjoint is implemented in FP64 only")
+        self.st = stepper
+        self.lib = stepper.lib
+        self.nsteps = int(nsteps)
+        self.every = int(ckpt_every)
+        g = ctypes.byref(stepper.grid)
+        self.ckpt_bytes = self.lib.dfw_checkpoint_bytes(g, stepper.code, self.nsteps, self.every)
+        self.ws_bytes = self.lib.dfw_adjoint_workspace_bytes(g, stepper.code, self.every)
+        if self.ws_bytes == 0 or self.every < 1 or self.nsteps < 0:
+            raise DFWError(_lib.DFW_EINVAL, "invalid adjoint configuration")
+        self.ckpt, self.ckpt_ptr = _aligned_buffer(self.ckpt_bytes, stepper.device)
+        self.ws, self.ws_ptr = _aligned_buffer(self.ws_bytes, stepper.device)
+        self.dt_hist = torch.zeros(max(self.nsteps, 1), dtype=torch.float64, device=stepper.device)
+        self.recorded = False
+
+    def forward(self, W: torch.Tensor, alpha: torch.Tensor, params: Params | None = None):
+        """Advance (W, alpha) in place by nsteps steps, storing checkpoints.  Returns (t, fail_step)."""
+        self.st._check(W, alpha)
+        p = (params or self.st.params).struct()
+        self.params = p
+        t = ctypes.c_double(0.0)
+        fs = ctypes.c_int32(-1)
+        st = self.lib.dfw_run_ckpt(_ptr(W), _ptr(alpha), ctypes.byref(self.st.grid), ctypes.byref(p), self.nsteps,
+                                   self.st.code, self.every, self.ckpt_ptr, self.ckpt_bytes, self.ws_ptr,
+                                   self.ws_bytes, _ptr(self.dt_hist), ctypes.byref(t), ctypes.byref(fs),
+                                   _stream_ptr(self.st.device))
+        if st != DFW_ENONPHYS:
+            _lib.check(st)
+        self.recorded = st == DFW_OK
+        return t.value, fs.value
+
+    def backward(self, gW: torch.Tensor, gA: torch.Tensor | None = None, want_alpha: bool = True):
+        """(dJ/dW^N, dJ/dalpha^N or None) -> (dJ/dW^0, dJ/dalpha^0 or None)."""
+        if not self.recorded:
+            raise RuntimeError("backward needs a successful forward")
+        self.st._check(gW, gA)
+        gW0 = torch.empty_like(gW)
+        gA0 = torch.empty_like(gW[0]) if want_alpha else None
+        _lib.check(self.lib.dfw_adjoint(ctypes.byref(self.st.grid), ctypes.byref(self.params), self.st.code,
+                                        self.nsteps, self.every, self.ckpt_ptr, self.ckpt_bytes, _ptr(self.dt_hist),
+                                        _ptr(gW), _ptr(gA) if gA is not None else None, _ptr(gW0),
+                                        _ptr(gA0) if gA0 is not None else None, self.ws_ptr, self.ws_bytes,
+                                        _stream_ptr(self.st.device)))
+        return gW0, gA0
+
+
+class Rollout(torch.autograd.Function):
+    """(W^N, alpha^N) = Rollout.apply(W0, alpha0, stepper, nsteps, ckpt_every): nsteps S2O4 steps
+    whose backward is the hand-written adjoint (checkpoint every ckpt_every steps, dt held at the
+    values of the forward).  A non-physical state in the forward raises DFWError."""
+
+    @staticmethod
+    def forward(ctx, W0, alpha0, stepper: Stepper, nsteps: int, ckpt_every: int = 10):
+        adj = Adjoint(stepper, nsteps, ckpt_every)
+        W = W0.detach().clone().contiguous()
+        A = alpha0.detach().clone().contiguous()
+        _, fs = adj.forward(W, A)
+        if fs != -1:
+            raise DFWError(DFW_ENONPHYS, f"non-physical state after {fs} steps")
+        ctx.adj = adj
+        return W, A
+
+    @staticmethod
+    def backward(ctx, gW, gA):
+        gW0, gA0 = ctx.adj.backward(gW.contiguous(), gA.contiguous() if gA is not None else None)
+        return gW0, gA0, None, None, None
+
+
+def rollout(W0: torch.Tensor, alpha0: torch.Tensor, stepper: Stepper, nsteps: int, ckpt_every: int = 10):
+    """Differentiable nsteps rollout: returns (W^N, alpha^N)."""
+    return Rollout.apply(W0, alpha0, stepper, nsteps, ckpt_every)
+
+
 class KernelProfile:
     """Context manager recording the device time of every kernel launched by Stepper.run (HIP
     events on the launch stream); .result() -> {kind: (total_ms, launches)}."""

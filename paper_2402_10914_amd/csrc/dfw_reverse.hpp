@@ -1,0 +1,587 @@
+// Reverse mode of the S2O4 step (adjoint kernels and their orchestration with step checkpointing).
+// Compiled inside dfw_step.hip, so it shares the forward kernels, the workspace helpers and the
+// error and profiling state of the library.
+//
+// The adjoint of one stage operator (U, alpha) -> (L, dL/dt, alpha_new), for given adjoints of its
+// outputs, takes two kernels:
+//   k_adj_faces   one workgroup per interface tile (the forward tiling; x and y interfaces in one
+//                 launch).  It stages the cells and alpha with a 4-row tangential halo in LDS,
+//                 recomputes the normal-sweep line values of TR+8 rows, runs the segment adjoint
+//                 (Gauss-point reconstruction, flux, DF) of TR+4 segment rows, sums for each row the
+//                 line adjoints of the five segments that read it (five LDS rounds in a fixed order),
+//                 runs the normal-sweep adjoint of the rows the tile owns, and writes per interface
+//                 and row the adjoints of the six cells of its normal stencil and of the two DFs it
+//                 reads: 26 values, each with exactly one writer (no atomics).
+//   k_adj_gather  one thread per cell: sums the interface-buffer entries whose stencil cell maps to
+//                 it (ghost cells fold back through the boundary map) in a fixed order, and applies
+//                 the stage recurrences of eq. (24) in reverse.
+// Results are bitwise reproducible and independent of the tile shape.
+#pragma once
+
+#include "dfw_adjoint.hpp"
+
+namespace dfw {
+
+constexpr int kAdjSlots = 26;  // 6 stencil cells x 4 components, then the DF of cells f-1 and f
+
+template <int TF, int TR>
+struct AdjTile {
+  static constexpr int NR = TR + 4;   // segment rows = threads per interface column
+  static constexpr int NT = TF * NR;  // threads per workgroup
+  static constexpr int NQ = TR + 8;   // normal-sweep rows
+  static constexpr int WN = TF + 5;   // cells along the normal
+  static constexpr int AN = TF + 3;   // alpha cells along the normal
+};
+
+// STAGE 1: seeds lam_L = dt/2 P + dt Q, lam_Lt = dt^2/8 P + dt^2/6 Q (P = adjoint of W*, Q = of R).
+// STAGE 2: seeds lam_Lt = dt^2/3 P (P = adjoint of W^{n+1}) and the adjoint LA of alpha^{n+1}, with
+//          the stage's interface DF products DX, DY.
+template <class real, int FLUX, int STAGE, int TF, int TR>
+__global__ __launch_bounds__(TF * (TR + 4)) void k_adj_faces(
+    const real* __restrict__ W, const real* __restrict__ alpha, const real* __restrict__ P,
+    const real* __restrict__ Q, const real* __restrict__ LA, const real* __restrict__ DX,
+    const real* __restrict__ DY, real* __restrict__ BX, real* __restrict__ BY, GridDesc G, Scheme S,
+    const double* __restrict__ dt_hist, int step) {
+  using T = AdjTile<TF, TR>;
+  __shared__ real sW[4][T::NQ][T::WN];
+  __shared__ real sA[T::NQ][T::AN];
+  __shared__ real sL[8][TF * T::NQ];
+
+  int b = blockIdx.x;
+  const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
+  const int dir = b < nbx ? 0 : 1;
+  if (dir) b -= nbx;
+  const int nx = G.nx, ny = G.ny;
+  const int Nn = dir ? ny : nx, Nt = dir ? nx : ny;
+  const int ntf = (Nn + 1 + TF - 1) / TF;
+  const int f0 = (b % ntf) * TF, t0 = (b / ntf) * TR;
+  const int bcn = dir ? G.bc_y : G.bc_x, bct = dir ? G.bc_x : G.bc_y;
+  const real inv_dn = real(dir ? G.inv_dy : G.inv_dx), inv_dt = real(dir ? G.inv_dx : G.inv_dy);
+  const size_t N = (size_t)nx * ny;
+  const int tid = threadIdx.x;
+  const real dt = real(dt_hist[step]);
+  const Coef<real> k = make_coef<real>(S);
+
+  // ---- stage cells (rows t0-4 .. t0+TR+3) and alpha in LDS, local component order
+  for (int e = tid; e < T::NQ * T::WN; e += T::NT) {
+    int nl, tl;
+    if (dir == 0) {
+      tl = e / T::WN;
+      nl = e % T::WN;
+    } else {
+      nl = e / T::NQ;
+      tl = e % T::NQ;
+    }
+    const int n = bc_map(f0 - 3 + nl, Nn, bcn), t = bc_map(t0 - 4 + tl, Nt, bct);
+    const size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
+    sW[0][tl][nl] = W[g];
+    sW[1][tl][nl] = W[(dir ? 2 : 1) * N + g];
+    sW[2][tl][nl] = W[(dir ? 1 : 2) * N + g];
+    sW[3][tl][nl] = W[3 * N + g];
+  }
+  for (int e = tid; e < T::NQ * T::AN; e += T::NT) {
+    int nl, tl;
+    if (dir == 0) {
+      tl = e / T::AN;
+      nl = e % T::AN;
+    } else {
+      nl = e / T::NQ;
+      tl = e % T::NQ;
+    }
+    const int n = bc_map(f0 - 2 + nl, Nn, bcn), t = bc_map(t0 - 4 + tl, Nt, bct);
+    sA[tl][nl] = alpha[dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t];
+  }
+  __syncthreads();
+
+  int fl, rr;
+  if (dir == 0) {
+    fl = tid % TF;
+    rr = tid / TF;
+  } else {
+    rr = tid % T::NR;
+    fl = tid / T::NR;
+  }
+  auto lidx = [&](int q, int c) { return dir == 0 ? q * TF + c : c * T::NQ + q; };
+  auto tidx = [&](int c, int r) { return dir == 0 ? r * TF + c : c * T::NR + r; };
+  const int f = f0 + fl;
+  const int t = t0 - 2 + rr;  // segment row of this thread
+  const bool face = f <= Nn;
+
+  // ---- normal sweep (forward) of the rows the segments read: own row q = rr+2, and four extra
+  //      rows (q = 0, 1, TR+6, TR+7) on the threads with rr < 4
+  real wln[4] = {0, 0, 0, 0}, wrn[4] = {0, 0, 0, 0};
+  auto ns_row = [&](int q, real* dl, real* dr) {
+    real cell[6][4];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][q][fl + m];
+    real wl[4], wr[4];
+    normal_sweep<real>(cell, sA[q][fl], sA[q][fl + 1], sA[q][fl + 2], sA[q][fl + 3], inv_dn, k, wl, wr, dl, dr);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sL[c][lidx(q, fl)] = wl[c];
+      sL[4 + c][lidx(q, fl)] = wr[c];
+    }
+  };
+  auto row_needed = [&](int q) {
+    const int tq = t0 - 4 + q;
+    return face && tq >= -2 && tq <= Nt + 1;
+  };
+  if (row_needed(rr + 2)) ns_row(rr + 2, wln, wrn);
+  if (rr < 4) {
+    const int q2 = rr < 2 ? rr : rr + TR + 4;
+    real dl[4], dr[4];
+    if (row_needed(q2)) ns_row(q2, dl, dr);
+  }
+  __syncthreads();
+
+  // ---- segment adjoint
+  const bool seg = face && t >= 0 && t < Nt;
+  real lwa[4] = {0, 0, 0, 0}, lwb[4] = {0, 0, 0, 0}, lwln[4] = {0, 0, 0, 0}, lwrn[4] = {0, 0, 0, 0};
+  real ll[2][5][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ll[s][m][c] = real(0);
+  real la_c[2] = {0, 0};
+  const int cmap[4] = {0, dir ? 2 : 1, dir ? 1 : 2, 3};
+  if (seg) {
+    // adjoints of the face sums from the cell seeds (face f: -1/dn to cell f-1, +1/dn to cell f)
+    const bool has_a = f >= 1, has_b = f < Nn;
+    const size_t ga = dir == 0 ? (size_t)t * nx + (f - 1) : (size_t)(f - 1) * nx + t;
+    const size_t gb = dir == 0 ? (size_t)t * nx + f : (size_t)f * nx + t;
+    real lF[4], lFt[4];
+    if (STAGE == 1) {
+      const real h1 = real(0.5) * dt, h2 = dt * dt * real(0.125), r2 = dt * dt * real(1.0 / 6.0);
+#pragma unroll
+      for (int gc = 0; gc < 4; ++gc) {
+        real La = 0, Lb = 0, Lta = 0, Ltb = 0;
+        if (has_a) {
+          const real p = P[gc * N + ga], q = Q[gc * N + ga];
+          La = h1 * p + dt * q;
+          Lta = h2 * p + r2 * q;
+        }
+        if (has_b) {
+          const real p = P[gc * N + gb], q = Q[gc * N + gb];
+          Lb = h1 * p + dt * q;
+          Ltb = h2 * p + r2 * q;
+        }
+        lF[gc] = (Lb - La) * inv_dn;
+        lFt[gc] = (Ltb - Lta) * inv_dn;
+      }
+    } else {
+      const real r3 = dt * dt * real(1.0 / 3.0);
+#pragma unroll
+      for (int gc = 0; gc < 4; ++gc) {
+        const real Lta = has_a ? r3 * P[gc * N + ga] : real(0);
+        const real Ltb = has_b ? r3 * P[gc * N + gb] : real(0);
+        lF[gc] = real(0);
+        lFt[gc] = (Ltb - Lta) * inv_dn;
+      }
+    }
+    real lFs[4], lFts[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      lFs[c] = real(0.5) * lF[cmap[c]];
+      lFts[c] = real(0.5) * lFt[cmap[c]];
+    }
+    // adjoint of the Gauss-point DF product: alpha_new of a cell is the product of its four faces
+    real ldfp = real(0);
+    if (STAGE == 2) {
+      const size_t rx = (size_t)nx + 1;
+      if (dir == 0) {
+        const int j = t;
+        if (has_a) {
+          const int i = f - 1;
+          ldfp += LA[(size_t)j * nx + i] * (DX[j * rx + i] * (DY[(size_t)j * nx + i] * DY[(size_t)(j + 1) * nx + i]));
+        }
+        if (has_b) {
+          const int i = f;
+          ldfp += LA[(size_t)j * nx + i] * (DX[j * rx + i + 1] * (DY[(size_t)j * nx + i] * DY[(size_t)(j + 1) * nx + i]));
+        }
+      } else {
+        const int i = t;
+        if (has_a) {
+          const int j = f - 1;
+          ldfp += LA[(size_t)j * nx + i] * (DY[(size_t)j * nx + i] * (DX[j * rx + i] * DX[j * rx + i + 1]));
+        }
+        if (has_b) {
+          const int j = f;
+          ldfp += LA[(size_t)j * nx + i] * (DY[(size_t)(j + 1) * nx + i] * (DX[j * rx + i] * DX[j * rx + i + 1]));
+        }
+      }
+    }
+    real wa[4], wb[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      wa[c] = sW[c][rr + 2][fl + 2];
+      wb[c] = sW[c][rr + 2][fl + 3];
+    }
+    real al[2][3];
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) al[side][q] = sA[rr + 1 + q][fl + 1 + side];
+    auto line = [&](int side, int m, int c) -> real { return sL[4 * side + c][lidx(rr + m, fl)]; };
+    segment_fluxes_adj<real, FLUX>(wa, wb, line, al, wln, wrn, dt, inv_dt, k, lFs, lFts, ldfp, lwa, lwb, ll, lwln,
+                                   lwrn, la_c);
+  }
+  __syncthreads();
+
+  // ---- line adjoints of each row: the five segments t+2-m (m = 0..4) that read it, in order of m
+  real acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sL[q][tid] = ll[q >> 2][m][q & 3];
+    __syncthreads();
+    const int src = rr + 2 - m;
+    if (src >= 0 && src < T::NR) {
+      const int st = tidx(fl, src);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += sL[q][st];
+    }
+    __syncthreads();
+  }
+
+  // ---- normal-sweep adjoint of the rows this tile owns: its TR rows, the two ghost rows below
+  //      the grid (first tile) and the two above it (tile of the last row)
+  const bool own = face && ((rr >= 2 && rr < TR + 2 && t < Nt) || (t0 == 0 && t < 0) ||
+                            (t >= Nt && t <= Nt + 1 && t0 + TR >= Nt));
+  if (!own) return;
+  real cell[6][4];
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][rr + 2][fl + m];
+  real lcell[6][4];
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lcell[m][c] = real(0);
+  real la1 = la_c[0], la2 = la_c[1];
+  normal_sweep_adj<real>(cell, sA[rr + 2][fl], sA[rr + 2][fl + 1], sA[rr + 2][fl + 2], sA[rr + 2][fl + 3], inv_dn, k,
+                         acc, acc + 4, lwln, lwrn, lcell, la1, la2);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    lcell[2][c] += lwa[c];
+    lcell[3][c] += lwb[c];
+  }
+  size_t sB;
+  real* o;
+  if (dir == 0) {
+    sB = (size_t)(ny + 4) * (nx + 1);
+    o = BX + (size_t)(t + 2) * (nx + 1) + f;
+  } else {
+    sB = (size_t)(ny + 1) * (nx + 4);
+    o = BY + (size_t)f * (nx + 4) + (t + 2);
+  }
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[(m * 4 + cmap[c]) * sB] = lcell[m][c];
+  o[24 * sB] = la1;
+  o[25 * sB] = la2;
+}
+
+// Indices in [lo, hi] that the boundary map sends to cell n of a line of Nn cells: a contiguous
+// range for transmissive boundaries, a stride-Nn progression for periodic ones.
+struct Preimages {
+  int first, stride, last;
+};
+
+__device__ __forceinline__ Preimages preimages(int n, int Nn, int bc, int lo, int hi) {
+  Preimages p;
+  if (bc == DFW_BC_PERIODIC) {
+    p.first = lo + (n - lo) % Nn;
+    p.stride = Nn;
+    p.last = hi;
+  } else {
+    p.first = n == 0 ? lo : n;
+    p.last = n == Nn - 1 ? hi : n;
+    p.stride = 1;
+  }
+  return p;
+}
+
+// Sum of the interface-buffer entries of one direction that belong to cell (n, t) (normal,
+// tangential index).  Entry (f, row) at slot s sits at B[s*sB + f*fs + (row+2)*rs].
+template <class real>
+__device__ __forceinline__ void gather_dir(const real* __restrict__ B, size_t sB, size_t fs, size_t rs, int n, int Nn,
+                                           int bcn, int t, int Nt, int bct, real* g, real& ga) {
+  const Preimages pt = preimages(t, Nt, bct, -2, Nt + 1);
+  const Preimages pn = preimages(n, Nn, bcn, -3, Nn + 2);
+  for (int tp = pt.first; tp <= pt.last; tp += pt.stride) {
+    const real* row = B + (size_t)(tp + 2) * rs;
+    for (int e = pn.first; e <= pn.last; e += pn.stride) {
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const int f = e + 3 - m;
+        if (f < 0 || f > Nn) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g[c] += row[(m * 4 + c) * sB + f * fs];
+      }
+      if (e + 1 >= 0 && e + 1 <= Nn) ga += row[24 * sB + (e + 1) * fs];
+      if (e >= 0 && e <= Nn) ga += row[25 * sB + e * fs];
+    }
+  }
+}
+
+// STAGE 2: LWs = adjoint of W* (from the stage-2 interfaces), LA = stage-2 part of the adjoint of
+//          alpha^n.
+// STAGE 1: LW <- LW + LWs + stage-1 part (adjoint of W^n), LA <- LA + stage-1 part.
+template <class real, int STAGE>
+__global__ __launch_bounds__(kCellBlock) void k_adj_gather(const real* __restrict__ BX, const real* __restrict__ BY,
+                                                           real* __restrict__ LW, real* __restrict__ LWs,
+                                                           real* __restrict__ LA, GridDesc G) {
+  const int nx = G.nx, ny = G.ny;
+  const size_t N = (size_t)nx * ny, o = (size_t)blockIdx.x * kCellBlock + threadIdx.x;
+  if (o >= N) return;
+  const int i = (int)(o % nx), j = (int)(o / nx);
+  real g[4] = {0, 0, 0, 0}, ga = 0;
+  gather_dir(BX, (size_t)(ny + 4) * (nx + 1), 1, (size_t)nx + 1, i, nx, G.bc_x, j, ny, G.bc_y, g, ga);
+  gather_dir(BY, (size_t)(ny + 1) * (nx + 4), (size_t)nx + 4, 1, j, ny, G.bc_y, i, nx, G.bc_x, g, ga);
+  if (STAGE == 2) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) LWs[c * N + o] = g[c];
+    LA[o] = ga;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) LW[c * N + o] = LW[c * N + o] + LWs[c * N + o] + g[c];
+    LA[o] = LA[o] + ga;
+  }
+}
+
+__global__ void k_set_dt(Ctrl* ctrl, const double* __restrict__ dt_hist, int step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->dt = dt_hist[step];
+}
+
+template <class real>
+__global__ __launch_bounds__(kCellBlock) void k_fill(real* __restrict__ x, real v, size_t n) {
+  const size_t o = (size_t)blockIdx.x * kCellBlock + threadIdx.x;
+  if (o < n) x[o] = v;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Host side.
+// ------------------------------------------------------------------------------------------------
+struct AdjShape {
+  int tf, tr;
+};
+// Interface tiles of the adjoint kernel, per flux (LF, GKS).
+static constexpr AdjShape kAdjShapes[2] = {{16, 28}, {16, 12}};
+
+static int adj_tiles(int flux, int nx, int ny) {
+  const AdjShape s = kAdjShapes[flux];
+  return ((nx + 1 + s.tf - 1) / s.tf) * ((ny + s.tr - 1) / s.tr) + ((ny + 1 + s.tf - 1) / s.tf) * ((nx + s.tr - 1) / s.tr);
+}
+
+template <class real, int FLUX, int STAGE>
+static void launch_adj_faces(const real* W, const real* A, const real* P, const real* Q, const real* LA,
+                             const real* DX, const real* DY, real* BX, real* BY, const GridDesc& G, const Scheme& S,
+                             const double* dt_hist, int step, hipStream_t st) {
+  constexpr int TF = kAdjShapes[FLUX].tf, TR = kAdjShapes[FLUX].tr;
+  hipLaunchKernelGGL((k_adj_faces<real, FLUX, STAGE, TF, TR>), dim3(adj_tiles(FLUX, G.nx, G.ny)), dim3(TF * (TR + 4)),
+                     0, st, W, A, P, Q, LA, DX, DY, BX, BY, G, S, dt_hist, step);
+}
+
+// Checkpoint store: one slot per segment of ckpt_every steps, slot = W (4N) | alpha (N).
+struct CkptLayout {
+  size_t w_off, a_off, slot, total;
+};
+
+static CkptLayout ckpt_layout(const dfw_grid* g, size_t es, int nsteps, int every) {
+  CkptLayout L;
+  const size_t N = (size_t)g->nx * g->ny;
+  L.w_off = 0;
+  L.a_off = align256(4 * N * es);
+  L.slot = L.a_off + align256(N * es);
+  const int nseg = nsteps > 0 ? (nsteps + every - 1) / every : 0;
+  L.total = (size_t)nseg * L.slot;
+  return L;
+}
+
+// Adjoint workspace: forward workspace | states of one segment | adjoint cells | interface buffers.
+struct AdjLayout {
+  WsLayout fwd;
+  size_t wst, ast, wss, dfx, dfy, lw, lws, la, bx, by, total;
+  size_t wN, aN, sx, sy;  // element strides of one step's W, alpha and DF planes
+};
+
+static AdjLayout adj_layout(const dfw_grid* g, size_t es, int every) {
+  AdjLayout L;
+  L.fwd = layout(g, es);
+  const size_t N = (size_t)g->nx * g->ny;
+  const size_t sx = (size_t)g->ny * (g->nx + 1), sy = (size_t)(g->ny + 1) * g->nx;
+  L.wN = align256(4 * N * es) / es;
+  L.aN = align256(N * es) / es;
+  L.sx = align256(sx * es) / es;
+  L.sy = align256(sy * es) / es;
+  size_t off = L.fwd.total;
+  L.wst = off;  // W^n of every step of a segment (the first comes from the checkpoint)
+  off += (size_t)every * L.wN * es;
+  L.ast = off;
+  off += (size_t)every * L.aN * es;
+  L.wss = off;  // W* of every step
+  off += (size_t)every * L.wN * es;
+  L.dfx = off;  // stage-2 interface DF products of every step
+  off += (size_t)every * L.sx * es;
+  L.dfy = off;
+  off += (size_t)every * L.sy * es;
+  L.lw = off;
+  off = align256(off + 4 * N * es);
+  L.lws = off;
+  off = align256(off + 4 * N * es);
+  L.la = off;
+  off = align256(off + N * es);
+  L.bx = off;
+  off = align256(off + (size_t)kAdjSlots * (g->ny + 4) * (g->nx + 1) * es);
+  L.by = off;
+  off = align256(off + (size_t)kAdjSlots * (g->ny + 1) * (g->nx + 4) * es);
+  L.total = off;
+  return L;
+}
+
+// Forward steps with checkpoints: the ordinary enqueue with a copy of (W, alpha) into slot n/every
+// before every step n that starts a segment.
+template <class real>
+static dfw_status run_ckpt_impl(real* W, real* A, const dfw_grid* g, const dfw_params* p, int nsteps, int every,
+                                char* ckpt, char* ws, double* dt_hist, double* t_out, int32_t* fail_step,
+                                hipStream_t st) {
+  const size_t es = sizeof(real);
+  const size_t N = (size_t)g->nx * g->ny;
+  WsLayout L = layout(g, es);
+  CkptLayout C = ckpt_layout(g, es, nsteps, every);
+  Ctrl* ctrl = (Ctrl*)(ws + L.ctrl_off);
+  const GridDesc G = make_desc(g);
+  auto hook = [&](int n) -> hipError_t {
+    if (n % every) return hipSuccess;
+    char* slot = ckpt + (size_t)(n / every) * C.slot;
+    hipError_t e = hipMemcpyAsync(slot + C.w_off, W, 4 * N * es, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(slot + C.a_off, A, N * es, hipMemcpyDeviceToDevice, st);
+    return e;
+  };
+  hipError_t he = hipSuccess;
+  enqueue_steps<real>(W, A, (real*)(ws + L.ws_off), (real*)(ws + L.r_off), (real*)(ws + L.fx_off),
+                      (real*)(ws + L.fy_off), ctrl, 1, G, nullptr, nullptr, shape_tiles(p->tile, g->nx, g->ny),
+                      nullptr, (int)cell_blocks(G), p, nsteps, dt_hist, st, [&](int n) {
+                        if (he == hipSuccess) he = hook(n);
+                      });
+  HIP_TRY(he);
+  HIP_TRY(hipGetLastError());
+  Ctrl h;
+  HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (t_out) *t_out = h.t;
+  if (fail_step) *fail_step = h.status ? h.fail_step : -1;
+  if (h.status) return fail(DFW_ENONPHYS, "non-physical state after " + std::to_string(h.fail_step) + " steps");
+  return DFW_OK;
+}
+
+template <class real, int FLUX>
+static dfw_status adjoint_impl(const dfw_grid* g, const dfw_params* p, int nsteps, int every, const char* ckpt,
+                               const double* dt_hist, const real* gW_final, const real* gA_final, real* gW0,
+                               real* gA0, char* ws, hipStream_t st) {
+  const size_t es = sizeof(real);
+  const size_t N = (size_t)g->nx * g->ny;
+  const AdjLayout L = adj_layout(g, es, every);
+  const CkptLayout C = ckpt_layout(g, es, nsteps, every);
+  const GridDesc G = make_desc(g);
+  const Scheme S = make_scheme(p);
+  Ctrl* ctrl = (Ctrl*)(ws + L.fwd.ctrl_off);
+  real* R = (real*)(ws + L.fwd.r_off);
+  real* FX = (real*)(ws + L.fwd.fx_off);
+  real* FY = (real*)(ws + L.fwd.fy_off);
+  real* LW = (real*)(ws + L.lw);
+  real* LWs = (real*)(ws + L.lws);
+  real* LA = (real*)(ws + L.la);
+  real* BX = (real*)(ws + L.bx);
+  real* BY = (real*)(ws + L.by);
+  auto Wst = [&](int l) { return (real*)(ws + L.wst) + (size_t)l * L.wN; };
+  auto Ast = [&](int l) { return (real*)(ws + L.ast) + (size_t)l * L.aN; };
+  auto Wss = [&](int l) { return (real*)(ws + L.wss) + (size_t)l * L.wN; };
+  auto DFX = [&](int l) { return (real*)(ws + L.dfx) + (size_t)l * L.sx; };
+  auto DFY = [&](int l) { return (real*)(ws + L.dfy) + (size_t)l * L.sy; };
+  const size_t sx = (size_t)g->ny * (g->nx + 1), sy = (size_t)(g->ny + 1) * g->nx;
+  const unsigned nb = cell_blocks(G);
+
+  FaceLaunch FL;
+  FL.shape = p->tile;
+  FL.flux = FLUX;
+  FL.nblocks = shape_tiles(p->tile, g->nx, g->ny);
+  FL.tiles = nullptr;
+  FL.grids = nullptr;
+  FL.G0 = G;
+  FL.ctrls = ctrl;
+  FL.S = S;
+  FL.dt_host = 0.0;
+  FL.lead = 0;  // dt from the control block, set from dt_hist before every step
+  FL.nsteps = nsteps;
+  FL.dt_hist = nullptr;
+
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, 1);
+  HIP_TRY(hipMemcpyAsync(LW, gW_final, 4 * N * es, hipMemcpyDeviceToDevice, st));
+  if (gA_final) HIP_TRY(hipMemcpyAsync(LA, gA_final, N * es, hipMemcpyDeviceToDevice, st));
+  else hipLaunchKernelGGL(k_fill<real>, dim3(nb), dim3(kCellBlock), 0, st, LA, real(0), N);
+
+  const int nseg = (nsteps + every - 1) / every;
+  for (int s = nseg - 1; s >= 0; --s) {
+    const int n0 = s * every, n1 = std::min(nsteps, n0 + every);
+    const char* slot = ckpt + (size_t)s * C.slot;
+    const real* W0 = (const real*)(slot + C.w_off);
+    const real* A0 = (const real*)(slot + C.a_off);
+    auto Wn = [&](int l) { return l == 0 ? W0 : (const real*)Wst(l); };
+    auto An = [&](int l) { return l == 0 ? A0 : (const real*)Ast(l); };
+    // recompute the segment, keeping W^n, alpha^n, W* and the stage-2 DF products of every step
+    for (int n = n0; n < n1; ++n) {
+      const int l = n - n0;
+      hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, st, ctrl, dt_hist, n);
+      FL.step = n;
+      FL.out = OUT_F | OUT_FT;
+      timed(DFW_K_FACES1, st, [&] { launch_faces<real>(FL, Wn(l), An(l), FX, FY, st); });
+      timed(DFW_K_UPDATE1, st, [&] {
+        hipLaunchKernelGGL(k_update1<real>, dim3(nb), dim3(kCellBlock), 0, st, Wn(l), FX, FY, Wss(l), R, ctrl, G,
+                           nullptr, nullptr);
+      });
+      FL.out = OUT_FT | OUT_DF;
+      timed(DFW_K_FACES2, st, [&] { launch_faces<real>(FL, Wss(l), An(l), FX, FY, st); });
+      HIP_TRY(hipMemcpyAsync(DFX(l), FX + 8 * sx, sx * es, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(DFY(l), FY + 8 * sy, sy * es, hipMemcpyDeviceToDevice, st));
+      if (n + 1 < n1)
+        timed(DFW_K_UPDATE2, st, [&] {
+          hipLaunchKernelGGL(k_update2<real>, dim3(nb), dim3(kCellBlock), 0, st, Wst(l + 1), Ast(l + 1), R, FX, FY,
+                             ctrl, G, nullptr, nullptr, S, n);
+        });
+    }
+    // reverse the steps of the segment
+    for (int n = n1 - 1; n >= n0; --n) {
+      const int l = n - n0;
+      timed(DFW_K_ADJ_FACES2, st, [&] {
+        launch_adj_faces<real, FLUX, 2>(Wss(l), An(l), LW, nullptr, LA, DFX(l), DFY(l), BX, BY, G, S, dt_hist, n, st);
+      });
+      timed(DFW_K_ADJ_GATHER, st, [&] {
+        hipLaunchKernelGGL((k_adj_gather<real, 2>), dim3(nb), dim3(kCellBlock), 0, st, BX, BY, LW, LWs, LA, G);
+      });
+      timed(DFW_K_ADJ_FACES1, st, [&] {
+        launch_adj_faces<real, FLUX, 1>(Wn(l), An(l), LWs, LW, nullptr, nullptr, nullptr, BX, BY, G, S, dt_hist, n,
+                                        st);
+      });
+      timed(DFW_K_ADJ_GATHER, st, [&] {
+        hipLaunchKernelGGL((k_adj_gather<real, 1>), dim3(nb), dim3(kCellBlock), 0, st, BX, BY, LW, LWs, LA, G);
+      });
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(gW0, LW, 4 * N * es, hipMemcpyDeviceToDevice, st));
+  if (gA0) HIP_TRY(hipMemcpyAsync(gA0, LA, N * es, hipMemcpyDeviceToDevice, st));
+  Ctrl h;
+  HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h.status) return fail(DFW_ENONPHYS, "non-physical state while recomputing the forward steps");
+  return DFW_OK;
+}
+
+}  // namespace dfw

@@ -659,11 +659,16 @@ static unsigned cell_blocks(const GridDesc& G) { return (unsigned)(((size_t)G.nx
 
 // The kernels of nsteps S2O4 steps on `st` (no synchronisation).  Single grid: grids/tiles/cblocks
 // are null and G0 describes the grid; batch: the tables describe every grid.
-template <class real>
+struct NoHook {
+  void operator()(int) const {}
+};
+
+// before_step(n) is called on the host before the kernels of step n are enqueued.
+template <class real, class Hook = NoHook>
 static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* FY, Ctrl* ctrls, int nctrl,
                           const GridDesc& G0, const GridDesc* grids, const int4* tiles, int ntiles,
                           const int2* cblocks, int ncblocks, const dfw_params* p, int nsteps, double* dt_hist,
-                          hipStream_t st) {
+                          hipStream_t st, Hook before_step = Hook()) {
   const Scheme S = make_scheme(p);
   FaceLaunch L;
   L.shape = p->tile;
@@ -682,6 +687,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
     hipLaunchKernelGGL(k_speed<real>, dim3(nb), dim3(kCellBlock), 0, st, W, ctrls, G0, grids, cblocks, S, 0);
   });
   for (int n = 0; n < nsteps; ++n) {
+    before_step(n);
     L.step = n;
     L.out = OUT_F | OUT_FT;
     L.lead = 1;
@@ -722,6 +728,8 @@ static dfw_status run_impl(real* W, real* A, const dfw_grid* g, const dfw_params
 }
 
 }  // namespace dfw
+
+#include "dfw_reverse.hpp"
 
 // ================================================================================================
 // Batched ragged grids.
@@ -1055,6 +1063,71 @@ void dfw_batch_free(dfw_batch* b) {
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->dtab) (void)hipFree(b->dtab);
   delete b;
+}
+
+// ---- reverse mode ----
+
+size_t dfw_checkpoint_bytes(const dfw_grid* grid, int32_t dtype, int32_t nsteps, int32_t ckpt_every) {
+  if (!grid || grid->nx < 1 || grid->ny < 1 || nsteps < 0 || ckpt_every < 1) return 0;
+  return ckpt_layout(grid, dtype == DFW_F32 ? 4 : 8, nsteps, ckpt_every).total;
+}
+
+static dfw_status check_ckpt(const dfw_grid* g, int32_t dtype, int32_t nsteps, int32_t every, const void* ckpt,
+                             size_t ckpt_bytes) {
+  if (every < 1) return fail(DFW_EINVAL, "ckpt_every must be >= 1");
+  if (nsteps < 0) return fail(DFW_EINVAL, "nsteps must be >= 0");
+  const size_t need = ckpt_layout(g, dtype == DFW_F32 ? 4 : 8, nsteps, every).total;
+  if (need && !ckpt) return fail(DFW_EINVAL, "checkpoint store is null");
+  if (((uintptr_t)ckpt) & 255) return fail(DFW_EINVAL, "checkpoint store must be 256-byte aligned");
+  if (ckpt_bytes < need) return fail(DFW_EINVAL, "checkpoint store too small: need " + std::to_string(need) + " bytes");
+  return DFW_OK;
+}
+
+dfw_status dfw_run_ckpt(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
+                        int32_t dtype, int32_t ckpt_every, void* ckpt, size_t ckpt_bytes, void* ws,
+                        size_t ws_bytes, double* dt_hist_dev, double* t_out, int32_t* fail_step, void* stream) {
+  dfw_status s = check_common(grid, params, dtype);
+  if (s != DFW_OK) return s;
+  if (!W || !alpha) return fail(DFW_EINVAL, "W and alpha must be non-null");
+  if (!dt_hist_dev && nsteps > 0) return fail(DFW_EINVAL, "dt_hist_dev is required");
+  if (!(params->dt_fixed > 0) && !(params->cfl > 0)) return fail(DFW_EINVAL, "need cfl > 0 or dt_fixed > 0");
+  if ((s = check_ckpt(grid, dtype, nsteps, ckpt_every, ckpt, ckpt_bytes)) != DFW_OK) return s;
+  if ((s = check_ws(grid, dtype, ws, ws_bytes)) != DFW_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == DFW_F64)
+    return run_ckpt_impl<double>((double*)W, (double*)alpha, grid, params, nsteps, ckpt_every, (char*)ckpt, (char*)ws,
+                                 dt_hist_dev, t_out, fail_step, st);
+  return run_ckpt_impl<float>((float*)W, (float*)alpha, grid, params, nsteps, ckpt_every, (char*)ckpt, (char*)ws,
+                              dt_hist_dev, t_out, fail_step, st);
+}
+
+size_t dfw_adjoint_workspace_bytes(const dfw_grid* grid, int32_t dtype, int32_t ckpt_every) {
+  if (!grid || grid->nx < 1 || grid->ny < 1 || ckpt_every < 1) return 0;
+  return adj_layout(grid, dtype == DFW_F32 ? 4 : 8, ckpt_every).total;
+}
+
+dfw_status dfw_adjoint(const dfw_grid* grid, const dfw_params* params, int32_t dtype, int32_t nsteps,
+                       int32_t ckpt_every, const void* ckpt, size_t ckpt_bytes, const double* dt_hist_dev,
+                       const void* gW_final, const void* gA_final, void* gW0, void* gA0, void* ws, size_t ws_bytes,
+                       void* stream) {
+  dfw_status s = check_common(grid, params, dtype);
+  if (s != DFW_OK) return s;
+  if (dtype != DFW_F64) return fail(DFW_EDTYPE, "the adjoint is implemented in FP64 only");
+  if (!gW_final || !gW0) return fail(DFW_EINVAL, "gW_final and gW0 must be non-null");
+  if (!dt_hist_dev && nsteps > 0) return fail(DFW_EINVAL, "dt_hist_dev is required");
+  if ((s = check_ckpt(grid, dtype, nsteps, ckpt_every, ckpt, ckpt_bytes)) != DFW_OK) return s;
+  if (!ws) return fail(DFW_EWORKSPACE, "workspace is null");
+  if (((uintptr_t)ws) & 255) return fail(DFW_EWORKSPACE, "workspace must be 256-byte aligned");
+  const size_t need = adj_layout(grid, 8, ckpt_every).total;
+  if (ws_bytes < need) return fail(DFW_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t st = (hipStream_t)stream;
+  if (params->flux == DFW_FLUX_LF)
+    return adjoint_impl<double, DFW_FLUX_LF>(grid, params, nsteps, ckpt_every, (const char*)ckpt, dt_hist_dev,
+                                             (const double*)gW_final, (const double*)gA_final, (double*)gW0,
+                                             (double*)gA0, (char*)ws, st);
+  return adjoint_impl<double, DFW_FLUX_GKS>(grid, params, nsteps, ckpt_every, (const char*)ckpt, dt_hist_dev,
+                                            (const double*)gW_final, (const double*)gA_final, (double*)gW0,
+                                            (double*)gA0, (char*)ws, st);
 }
 
 // ---- measurement ----

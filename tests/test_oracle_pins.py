@@ -536,3 +536,44 @@ def test_tangent_matches_central_differences(flux):
 
     e6, e7 = fd(1e-6), fd(1e-7)
     assert e7 < 1e-5 and e7 < e6 / 10, (e6, e7)
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_tangent_of_alpha_and_df_branch_matches_central_differences(flux):
+    """The forward-mode derivative of both outputs (W^N and alpha^N) along a direction in both
+    inputs (W^0 and alpha^0), on cell-wise random states with part of the grid on the DF branch of
+    eq. (34), against central differences of the oracle's own steps (fixed dt): the gap at
+    h = 1e-6 is below 1e-6 relative.  Pressure and velocity vary from cell to cell so that no
+    kink argument (|p_l - p_r|, the LF speed max) sits at zero."""
+    rng = np.random.default_rng(71)
+    nx, ny = 7, 6
+    rho = 1.0 + 0.2 * rng.random((ny, nx))
+    p = 1.0 + 0.3 * rng.random((ny, nx))
+    rho[2:5, 3:6] *= 3.0
+    p[2:5, 3:6] *= 2.0
+    u = 1.0 + 0.2 * rng.standard_normal((ny, nx))
+    v = 0.5 + 0.2 * rng.standard_normal((ny, nx))
+    W0 = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    a0 = rng.uniform(0.6, 1.0, (ny, nx))
+    a0[1:5, 1:4] = rng.uniform(0.1, 0.45, (4, 3))
+    g = O.make_grid(nx, ny, 2.0 / nx, 2.0 / ny, O.BC_PERIODIC)
+    smax, ok = O.max_speed(W0, g, O.make_params())
+    assert ok
+    dt = 0.4 / smax
+    prm = O.make_params(flux=flux, dt_fixed=dt)
+    gW = rng.standard_normal(W0.shape)
+    gA = rng.standard_normal(a0.shape)
+    vW = rng.standard_normal(W0.shape)
+    vA = 0.01 * rng.standard_normal(a0.shape)
+    n = 3
+    _, _, dW, dA = O.run_tangent(W0, a0, vW, vA, g, prm, [dt] * n)
+    tan = float((gW * dW).sum() + (gA * dA).sum())
+    assert abs((gA * dA).sum()) > 1e-2 * abs(tan)  # alpha^N carries a real part of the derivative
+
+    def J(h):
+        Wn, An, _, _, fs = O.run(W0 + h * vW, a0 + h * vA, g, prm, n)
+        assert fs == -1
+        return float((gW * Wn).sum() + (gA * An).sum())
+
+    fd = (J(1e-6) - J(-1e-6)) / 2e-6
+    assert abs(fd - tan) <= 1e-6 * abs(tan), (fd, tan)
