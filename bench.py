@@ -12,6 +12,9 @@ Prints one JSON line: cell-updates/s, per-kernel roofline of the dominant kernel
 bound: its algorithmic flops per launch over its mean launch time, measured with HIP events on the
 launch stream) and the CPU oracle timed on a bounded sample on this host.
 
+Also reported: the batched form against the per-grid loop ("batched") and the cost of the
+gradient of a 100-step rollout against the rollout itself ("adjoint").
+
 Other modes:  --mode copy   plain device copy of known size (calibrates rocprofv3 FETCH/WRITE_SIZE).
 """
 import argparse
@@ -122,6 +125,55 @@ def batch_compare(nsteps=100, tune=True):
             "graph_ms": t_graph * 1e3, "loop_ms": t_loop * 1e3, "failed_grids": sum(1 for f in fs if f != -1)}
 
 
+def adjoint_compare(n=1024, nsteps=100, every=10):
+    """Adjoint workload (FP64, n x n periodic density wave plus 16 Gaussian bumps, LF, CFL 0.5,
+    nsteps steps, checkpoint every `every` steps, loss = L2 misfit of the final density to a seeded
+    target): time of the gradient (segment recomputation and reverse sweep) over the time of the
+    plain forward rollout."""
+    import torch
+    from paper_2402_10914_amd import api
+    from paper_2402_10914_amd import workloads as WL
+    prob = WL.bumps(n, seed=1024, cfl=0.5, nsteps=nsteps)
+    st = api.Stepper.for_problem(prob, api.Params(flux=api.FLUX_LF, cfl=0.5))
+    W0 = torch.tensor(prob.W, device="cuda")
+    A0 = torch.tensor(prob.alpha, device="cuda")
+    adj = api.Adjoint(st, nsteps, every)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    W, A = W0.clone(), A0.clone()
+    st.run(W, A, 2)  # warm
+    W, A = W0.clone(), A0.clone()
+    t_fwd, (t_sim, fs) = timed(lambda: st.run(W, A, nsteps))
+    W, A = W0.clone(), A0.clone()
+    t_fwd_ckpt, _ = timed(lambda: adj.forward(W, A))
+    target = torch.tensor(WL.bumps_target(n, t_sim, seed=1025), device="cuda")
+    area = prob.dx * prob.dy
+    gW = torch.zeros_like(W)
+    gW[0] = area * (W[0] - target)
+    loss = 0.5 * area * float(((W[0] - target) ** 2).sum())
+    adj.backward(gW, None)  # warm
+    t_bwd, (gW0, _) = timed(lambda: adj.backward(gW, None))
+    with api.KernelProfile() as kp:
+        adj.backward(gW, None)
+    prof = kp.result()
+    kernels = {k: {"avg_us": round(1e3 * ms / c, 2), "launches": c, "total_ms": round(ms, 3)}
+               for k, (ms, c) in prof.items() if c}
+    recompute_ms = sum(prof[k][0] for k in ("faces1", "update1", "faces2", "update2"))
+    reverse_ms = sum(prof[k][0] for k in ("adj_faces1", "adj_faces2", "adj_gather"))
+    return {"grid": f"{n}x{n}", "steps": nsteps, "ckpt_every": every, "flux": "lf", "dtype": "f64",
+            "forward_ms": round(t_fwd * 1e3, 2), "forward_with_checkpoints_ms": round(t_fwd_ckpt * 1e3, 2),
+            "gradient_ms": round(t_bwd * 1e3, 2), "ratio_gradient_over_forward": round(t_bwd / t_fwd, 3),
+            "recompute_kernels_ms": round(recompute_ms, 2), "reverse_kernels_ms": round(reverse_ms, 2),
+            "loss": loss, "grad_norm": float(gW0.norm()), "fail_step": fs,
+            "checkpoint_bytes": adj.ckpt_bytes, "workspace_bytes": adj.ws_bytes, "kernels": kernels}
+
+
 def copy_mode(args):
     import torch
     n = 1 << 26  # 64 Mi doubles = 512 MiB each way
@@ -147,6 +199,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--mode", default="step", choices=["step", "copy"])
     args = ap.parse_args()
 
@@ -237,6 +290,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps),
         "batched": None if args.no_batch else batch_compare(),
+        "adjoint": None if args.no_adjoint else adjoint_compare(),
     }
     print(json.dumps(out))
 

@@ -476,8 +476,9 @@ static dfw_status run_ckpt_impl(real* W, real* A, const dfw_grid* g, const dfw_p
   HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (t_out) *t_out = h.t;
-  if (fail_step) *fail_step = h.status ? h.fail_step : -1;
-  if (h.status) return fail(DFW_ENONPHYS, "non-physical state after " + std::to_string(h.fail_step) + " steps");
+  if (fail_step) *fail_step = h.fail_at != kNoFail ? h.fail_at : -1;
+  if (h.fail_at != kNoFail)
+    return fail(DFW_ENONPHYS, "non-physical state after " + std::to_string(h.fail_at) + " steps");
   return DFW_OK;
 }
 
@@ -544,7 +545,7 @@ static dfw_status adjoint_impl(const dfw_grid* g, const dfw_params* p, int nstep
       timed(DFW_K_FACES1, st, [&] { launch_faces<real>(FL, Wn(l), An(l), FX, FY, st); });
       timed(DFW_K_UPDATE1, st, [&] {
         hipLaunchKernelGGL(k_update1<real>, dim3(nb), dim3(kCellBlock), 0, st, Wn(l), FX, FY, Wss(l), R, ctrl, G,
-                           nullptr, nullptr);
+                           nullptr, nullptr, n);
       });
       FL.out = OUT_FT | OUT_DF;
       timed(DFW_K_FACES2, st, [&] { launch_faces<real>(FL, Wss(l), An(l), FX, FY, st); });
@@ -580,7 +581,7 @@ static dfw_status adjoint_impl(const dfw_grid* g, const dfw_params* p, int nstep
   Ctrl h;
   HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (h.status) return fail(DFW_ENONPHYS, "non-physical state while recomputing the forward steps");
+  if (h.fail_at != kNoFail) return fail(DFW_ENONPHYS, "non-physical state while recomputing the forward steps");
   return DFW_OK;
 }
 

@@ -37,10 +37,11 @@ struct Ctrl {
   unsigned long long smax_bits[2];  // running max signal speed / dx for the next step (ping-pong)
   double dt;                        // dt of the current step
   double t;                         // accumulated time
-  int status;                       // 0 ok, 1 non-physical state met
-  int fail_step;                    // completed steps when status was raised
-  int pad[2];
+  int fail_at;                      // steps completed when a non-physical state was first met,
+                                    // kNoFail if none; kernels of step n skip once fail_at <= n
+  int pad[3];
 };
+constexpr int kNoFail = 0x7fffffff;
 
 // One grid: sizes, spacing, boundaries and element offsets of its arrays inside the (packed) state,
 // alpha, stage and interface buffers.
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
     lead_tile = blockIdx.x == 0;
   }
   Ctrl* ctrl = ctrls + gi;
-  if (ctrl->status) return;
+  if (ctrl->fail_at <= step) return;
   const int nx = G.nx, ny = G.ny;
   const real* W = Wall + G.w_off;
   const real* alpha = Aall + G.a_off;
@@ -312,10 +313,10 @@ __global__ __launch_bounds__(kCellBlock) void k_update1(const real* __restrict__
                                                         const real* __restrict__ FYall, real* __restrict__ Wsall,
                                                         real* __restrict__ Rall, Ctrl* __restrict__ ctrls, GridDesc G0,
                                                         const GridDesc* __restrict__ grids,
-                                                        const int2* __restrict__ cblocks) {
+                                                        const int2* __restrict__ cblocks, int step) {
   const CellCtx C = cell_ctx(G0, grids, cblocks);
   Ctrl* ctrl = ctrls + C.gi;
-  if (ctrl->status || !C.live) return;
+  if (ctrl->fail_at <= step || !C.live) return;
   const GridDesc& G = C.G;
   const size_t N = (size_t)G.nx * G.ny, o = C.o;
   const int i = (int)(o % G.nx), j = (int)(o / G.nx);
@@ -348,7 +349,10 @@ __device__ __forceinline__ bool cell_speed(const real* w, const Scheme& S, const
   return ok;
 }
 
-// Workgroup max of a non-negative double and OR of a flag, then one atomic each.
+// Workgroup max of a non-negative double and OR of a flag, then one atomic each.  A flag records
+// step_done as the failing step; it stops the kernels of later steps only, so every workgroup of
+// the launch that finds it still writes its cells and the stored state does not depend on the
+// order in which workgroups run.
 __device__ __forceinline__ void block_reduce_commit(double s, int bad, Ctrl* ctrl, int slot, int step_done) {
   __shared__ double red[kCellBlock / 64];
   __shared__ int redb[kCellBlock / 64];
@@ -369,9 +373,7 @@ __device__ __forceinline__ void block_reduce_commit(double s, int bad, Ctrl* ctr
       bad |= redb[q];
     }
     if (s > 0.0) atomicMax(&ctrl->smax_bits[slot], (unsigned long long)__double_as_longlong(s));
-    if (bad) {
-      if (atomicCAS(&ctrl->status, 0, 1) == 0) ctrl->fail_step = step_done;
-    }
+    if (bad) atomicMin(&ctrl->fail_at, step_done);
   }
 }
 
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(kCellBlock) void k_update2(real* __restrict__ Wall,
                                                         const int2* __restrict__ cblocks, Scheme S, int step) {
   const CellCtx C = cell_ctx(G0, grids, cblocks);
   Ctrl* ctrl = ctrls + C.gi;
-  if (ctrl->status) return;  // uniform over the workgroup: one grid per workgroup
+  if (ctrl->fail_at <= step) return;  // uniform over the workgroup: one grid per workgroup
   const GridDesc& G = C.G;
   double s = 0.0;
   int bad = 0;
@@ -440,8 +442,7 @@ __global__ void k_ctrl_init(Ctrl* ctrls, int n) {
   c->smax_bits[1] = 0ull;
   c->dt = 0.0;
   c->t = 0.0;
-  c->status = 0;
-  c->fail_step = -1;
+  c->fail_at = kNoFail;
 }
 
 template <class real>
@@ -695,7 +696,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
     timed(DFW_K_FACES1, st, [&] { launch_faces<real>(L, W, A, FX, FY, st); });
     timed(DFW_K_UPDATE1, st, [&] {
       hipLaunchKernelGGL(k_update1<real>, dim3(nb), dim3(kCellBlock), 0, st, W, FX, FY, Ws, R, ctrls, G0, grids,
-                         cblocks);
+                         cblocks, n);
     });
     L.out = OUT_FT | OUT_DF;
     L.lead = 0;
@@ -722,8 +723,9 @@ static dfw_status run_impl(real* W, real* A, const dfw_grid* g, const dfw_params
   HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (t_out) *t_out = h.t;
-  if (fail_step) *fail_step = h.status ? h.fail_step : -1;
-  if (h.status) return fail(DFW_ENONPHYS, "non-physical state after " + std::to_string(h.fail_step) + " steps");
+  if (fail_step) *fail_step = h.fail_at != kNoFail ? h.fail_at : -1;
+  if (h.fail_at != kNoFail)
+    return fail(DFW_ENONPHYS, "non-physical state after " + std::to_string(h.fail_at) + " steps");
   return DFW_OK;
 }
 
@@ -866,7 +868,7 @@ dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* 
   double v;
   std::memcpy(&v, &h.smax_bits[0], sizeof(double));
   if (smax) *smax = v;
-  if (nonphys) *nonphys = h.status ? 1 : 0;
+  if (nonphys) *nonphys = h.fail_at != kNoFail ? 1 : 0;
   return DFW_OK;
 }
 
@@ -1050,8 +1052,8 @@ dfw_status dfw_batch_run(dfw_batch* b, void* W_flat, void* alpha_flat, int32_t n
   int nbad = 0;
   for (int g = 0; g < b->ngrids; ++g) {
     if (t_out) t_out[g] = h[g].t;
-    if (fail_steps) fail_steps[g] = h[g].status ? h[g].fail_step : -1;
-    nbad += h[g].status ? 1 : 0;
+    if (fail_steps) fail_steps[g] = h[g].fail_at != kNoFail ? h[g].fail_at : -1;
+    nbad += h[g].fail_at != kNoFail ? 1 : 0;
   }
   if (nbad) return fail(DFW_ENONPHYS, std::to_string(nbad) + " grid(s) met a non-physical state");
   return DFW_OK;
