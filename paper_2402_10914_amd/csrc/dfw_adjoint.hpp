@@ -87,29 +87,131 @@ DFW_HD void project_adj(const Basis<real>& B, const real* w, const real* lq, rea
   lw[3] += -lX;
 }
 
+// unproject_adj in two parts: lq += R^T lw does not depend on q; the basis part does.
 template <class real>
-DFW_HD void unproject_adj(const Basis<real>& B, const real* q, const real* lw, real* lq, BasisAdj<real>& lB) {
-  real w0 = q[0] + q[1] + q[3];
-  real dq = q[3] - q[0];
+DFW_HD void unproject_adj_q(const Basis<real>& B, const real* lw, real* lq) {
   real lw0 = lw[0] + B.u * lw[1] + B.v * lw[2];
   real ldq = B.c * lw[1] + B.u * B.c * lw[3];
-  lB.u += lw[1] * w0 + lw[3] * B.c * dq;
-  lB.c += lw[1] * dq + lw[3] * B.u * dq;
-  lB.v += lw[2] * w0 + lw[3] * q[2];
-  lB.H += lw[3] * (q[0] + q[3]);
-  lB.hq2 += lw[3] * q[1];
   lq[0] += lw0 - ldq + lw[3] * B.H;
   lq[1] += lw0 + lw[3] * B.hq2;
   lq[2] += lw[2] + lw[3] * B.v;
   lq[3] += lw0 + ldq + lw[3] * B.H;
 }
 
+template <class real>
+DFW_HD void unproject_adj_B(const Basis<real>& B, const real* q, const real* lw, BasisAdj<real>& lB) {
+  real w0 = q[0] + q[1] + q[3];
+  real dq = q[3] - q[0];
+  lB.u += lw[1] * w0 + lw[3] * B.c * dq;
+  lB.c += lw[1] * dq + lw[3] * B.u * dq;
+  lB.v += lw[2] * w0 + lw[3] * q[2];
+  lB.H += lw[3] * (q[0] + q[3]);
+  lB.hq2 += lw[3] * q[1];
+}
+
+template <class real>
+DFW_HD void unproject_adj(const Basis<real>& B, const real* q, const real* lw, real* lq, BasisAdj<real>& lB) {
+  unproject_adj_B(B, q, lw, lB);
+  unproject_adj_q(B, lw, lq);
+}
+
+template <class real>
+DFW_HD void basis_adj_add(BasisAdj<real>& a, const BasisAdj<real>& b) {
+  a.u += b.u;
+  a.v += b.v;
+  a.c += b.c;
+  a.ic += b.ic;
+  a.H += b.H;
+  a.hq2 += b.hq2;
+  a.b1 += b.b1;
+  a.b2 += b.b2;
+}
+
+// Component C of project(B, w), and its adjoint (the four adjoints sum to project_adj).
+template <int C, class real>
+DFW_HD real project_comp(const Basis<real>& B, const real* w) {
+  if (C == 2) return w[2] - B.v * w[0];
+  const real T = B.b2 * w[0] - B.b1 * (B.u * w[1] + B.v * w[2] - w[3]);
+  if (C == 1) return w[0] - T;
+  const real s = (B.u * w[0] - w[1]) * B.ic;
+  return C == 0 ? real(0.5) * (T + s) : real(0.5) * (T - s);
+}
+
+template <int C, class real>
+DFW_HD void project_adj_comp(const Basis<real>& B, const real* w, real lqc, real* lw, BasisAdj<real>& lB) {
+  if (C == 2) {
+    lw[2] += lqc;
+    lw[0] += -B.v * lqc;
+    lB.v += -w[0] * lqc;
+    return;
+  }
+  real lT, ls = real(0);
+  if (C == 1) {
+    lw[0] += lqc;
+    lT = -lqc;
+  } else {
+    lT = real(0.5) * lqc;
+    ls = C == 0 ? real(0.5) * lqc : real(-0.5) * lqc;
+  }
+  if (C != 1) {
+    lB.u += ls * w[0] * B.ic;
+    lw[0] += ls * B.u * B.ic;
+    lw[1] += -ls * B.ic;
+    lB.ic += ls * (B.u * w[0] - w[1]);
+  }
+  const real X = B.u * w[1] + B.v * w[2] - w[3];
+  lB.b2 += lT * w[0];
+  lw[0] += lT * B.b2;
+  lB.b1 += -lT * X;
+  const real lX = -lT * B.b1;
+  lB.u += lX * w[1];
+  lw[1] += lX * B.u;
+  lB.v += lX * w[2];
+  lw[2] += lX * B.v;
+  lw[3] += -lX;
+}
+
+// Component C of R^T lw (the part of unproject_adj that does not depend on q).
+template <int C, class real>
+DFW_HD real unproject_adj_q_comp(const Basis<real>& B, const real* lw) {
+  if (C == 2) return lw[2] + lw[3] * B.v;
+  const real lw0 = lw[0] + B.u * lw[1] + B.v * lw[2];
+  if (C == 1) return lw0 + lw[3] * B.hq2;
+  const real ldq = B.c * lw[1] + B.u * B.c * lw[3];
+  return C == 0 ? lw0 - ldq + lw[3] * B.H : lw0 + ldq + lw[3] * B.H;
+}
+
+// Basis part of unproject_adj for component C of q alone (the four parts sum to unproject_adj_B).
+template <int C, class real>
+DFW_HD void unproject_adj_B_comp(const Basis<real>& B, real qc, const real* lw, BasisAdj<real>& lB) {
+  if (C == 0) {
+    lB.u += lw[1] * qc - lw[3] * B.c * qc;
+    lB.c += -lw[1] * qc - lw[3] * B.u * qc;
+    lB.v += lw[2] * qc;
+    lB.H += lw[3] * qc;
+  } else if (C == 1) {
+    lB.u += lw[1] * qc;
+    lB.v += lw[2] * qc;
+    lB.hq2 += lw[3] * qc;
+  } else if (C == 2) {
+    lB.v += lw[3] * qc;
+  } else {
+    lB.u += lw[1] * qc + lw[3] * B.c * qc;
+    lB.c += lw[1] * qc + lw[3] * B.u * qc;
+    lB.v += lw[2] * qc;
+    lB.H += lw[3] * qc;
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Hybrid reconstruction: lP (NDEG coefficients) -> lQ (5) and the DF of the centre cell (DF branch).
+// With a non-null P it also stores the forward polynomial (the same NDEG coefficients recon_poly
+// gives, up to rounding: the reverse divides once per smoothness indicator and reuses the
+// reciprocals).
 // ------------------------------------------------------------------------------------------------
 template <class real, int NDEG>
 DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, const real* lP, real* lQ,
-                           real& la_c) {
+                           real& la_c, real* P = nullptr) {
   const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
   const real i6 = real(1.0 / 6.0);
   real p1_0 = (real(5) * Q2 + real(2) * Q3 - Q1) * i6;
@@ -123,6 +225,13 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
   if (amax < k.alpha_thres) {
     la_c += lP0 * (p1_0 - Q2) + lP1 * p1_1 + lP2 * p1_2;
     lQ[2] += lP0 * (real(1) - a_c);
+    if (P) {
+      P[0] = Q2 + a_c * (p1_0 - Q2);
+      if (NDEG > 1) P[1] = a_c * p1_1;
+      if (NDEG > 2) P[2] = a_c * p1_2;
+      if (NDEG > 3) P[3] = real(0);
+      if (NDEG > 4) P[4] = real(0);
+    }
     l10 = a_c * lP0;
     l11 = a_c * lP1;
     l12 = a_c * lP2;
@@ -154,10 +263,11 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
     real b3 = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 + real(1421461.0 / 2275.0) * u4 * u4;
     real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
     real be[4] = {b0 + k.eps, b1 + k.eps, b2 + k.eps, b3 + k.eps};
-    real r[4], w[4];
+    real ib[4], r[4], w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      r[q] = tau / be[q];
+      ib[q] = real(1) / be[q];
+      r[q] = tau * ib[q];
       w[q] = k.d[q] * (real(1) + r[q] * r[q]);
     }
     real iws = real(1) / (w[0] + w[1] + w[2] + w[3]);
@@ -166,6 +276,13 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
     real g1 = w[1] * iws - g3 * k.dr[1];
     real g2 = w[2] * iws - g3 * k.dr[2];
     real h3 = g3 * k.inv_d3;
+    if (P) {
+      P[0] = g0 * p0_0 + g1 * p1_0 + g2 * p2_0 + h3 * c0;
+      if (NDEG > 1) P[1] = g0 * p0_1 + g1 * p1_1 + g2 * p2_1 + h3 * c1;
+      if (NDEG > 2) P[2] = g0 * p0_2 + g1 * p1_2 + g2 * p2_2 + h3 * c2;
+      if (NDEG > 3) P[3] = h3 * c3;
+      if (NDEG > 4) P[4] = h3 * c4;
+    }
     // reverse of P
     real lg0 = lP0 * p0_0 + lP1 * p0_1 + lP2 * p0_2;
     real lg1 = lP0 * p1_0 + lP1 * p1_1 + lP2 * p1_2;
@@ -186,9 +303,9 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       lw[q] += lS;
-      real lr = lw[q] * k.d[q] * real(2) * r[q];
-      ltau += lr / be[q];
-      lb[q] = -lr * r[q] / be[q];
+      real lr = lw[q] * k.d[q] * real(2) * r[q] * ib[q];
+      ltau += lr;
+      lb[q] = -lr * r[q];
     }
     real s30 = sgn(b3 - b0), s31 = sgn(b3 - b1), s32 = sgn(b3 - b2);
     real lt3 = ltau * real(1.0 / 3.0);
@@ -892,186 +1009,187 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
 }
 
 // ------------------------------------------------------------------------------------------------
-// Segment and normal-sweep adjoints (reverse of segment_fluxes and normal_sweep).
+// One side of the normal sweep and of an interface segment, forward and reverse.
+//
+// The interface kernels split the work of an interface segment over two threads, one per side:
+// side 0 reconstructs cell f-1 (left state), side 1 cell f (right state).  The two sides share the
+// characteristic basis of the segment (cells f-1 and f); they meet only in the flux and DF of each
+// Gauss point and in the adjoint of the basis.
 // ------------------------------------------------------------------------------------------------
-// Inputs as segment_fluxes plus the adjoints of its outputs (sums over the two Gauss points of
-// the flux and its time derivative, and the Gauss-point DF product).  Outputs (accumulated):
-// adjoints of the basis cells wa, wb, of the line values line(side, m, c) as ll[side][m][c], of the
-// normal derivatives, and of the DF of the same-side centre cells la_c[side] (DF branch only).
-template <class real, int FLUX, class LineFn>
-DFW_HD void segment_fluxes_adj(const real* wa, const real* wb, LineFn line, const real (*alpha)[3], const real* wln,
-                               const real* wrn, real dt, real inv_dt, const Coef<real>& k, const real* lFs,
-                               const real* lFts, real ldfp, real* lwa, real* lwb, real (*ll)[5][4], real* lwln,
-                               real* lwrn, real* la_c) {
-  Basis<real> B = make_basis(wa, wb, k);
-  real gw[2][2][4], gwt[2][2][4], qv[2][2][4], qd[2][2][4];
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    real Q[5][4];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      real w[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) w[c] = line(side, m, c);
-      project(B, w, Q[m]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      real s[5], Pc[5];
-#pragma unroll
-      for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-      recon_poly<real, 5>(s, alpha[side][0], alpha[side][1], alpha[side][2], k, Pc);
-      real v0, d0, v1, d1;
-      eval_poly_at(Pc, real(kXiGp0), v0, d0);
-      eval_poly_at(Pc, real(kXiGp1), v1, d1);
-      qv[side][0][c] = v0;
-      qv[side][1][c] = v1;
-      qd[side][0][c] = d0 * inv_dt;
-      qd[side][1][c] = d1 * inv_dt;
-    }
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      unproject(B, qv[side][g], gw[side][g]);
-      unproject(B, qd[side][g], gwt[side][g]);
-    }
-  }
-  // per Gauss point: flux and DF adjoints -> states
-  real lgw[2][2][4], lgwt[2][2][4];
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int g = 0; g < 2; ++g)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) lgw[s][g][c] = lgwt[s][g][c] = real(0);
-  Prim<real> qg[2][2];
-#pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    qg[0][g] = prim(gw[0][g], k);
-    qg[1][g] = prim(gw[1][g], k);
-  }
-  real dfg[2] = {df_factor(qg[0][0], qg[1][0]), df_factor(qg[0][1], qg[1][1])};
-#pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    PrimAdj<real> lql, lqr;
-    lql.zero();
-    lqr.zero();
-    if (FLUX == 0)
-      lf_flux_adj(gw[0][g], wln, gwt[0][g], gw[1][g], wrn, gwt[1][g], qg[0][g], qg[1][g], k, lFs, lFts, lgw[0][g], lwln,
-                  lgwt[0][g], lgw[1][g], lwrn, lgwt[1][g], lql, lqr);
-    else
-      gks_flux_adj(gw[0][g], wln, gwt[0][g], gw[1][g], wrn, gwt[1][g], qg[0][g], qg[1][g], dt, k, lFs, lFts, lgw[0][g],
-                   lwln, lgwt[0][g], lgw[1][g], lwrn, lgwt[1][g], lql, lqr);
-    df_factor_adj(qg[0][g], qg[1][g], ldfp * dfg[1 - g], lql, lqr);
-    prim_adj(gw[0][g], qg[0][g], k, lql, lgw[0][g]);
-    prim_adj(gw[1][g], qg[1][g], k, lqr, lgw[1][g]);
-  }
-  // states at the Gauss points -> reconstruction -> line values
-  BasisAdj<real> lB;
-  lB.zero();
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    real lqv[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, lqd[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      unproject_adj(B, qv[side][g], lgw[side][g], lqv[g], lB);
-      unproject_adj(B, qd[side][g], lgwt[side][g], lqd[g], lB);
-    }
-    real Q[5][4], lQ[5][4];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      real w[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        w[c] = line(side, m, c);
-        lQ[m][c] = real(0);
-      }
-      project(B, w, Q[m]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      real s[5], lP[5] = {0, 0, 0, 0, 0}, lQc[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-      for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-      eval_poly_at_adj(real(kXiGp0), lqv[0][c], lqd[0][c] * inv_dt, lP);
-      eval_poly_at_adj(real(kXiGp1), lqv[1][c], lqd[1][c] * inv_dt, lP);
-      recon_poly_adj<real, 5>(s, alpha[side][0], alpha[side][1], alpha[side][2], k, lP, lQc, la_c[side]);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) lQ[m][c] = lQc[m];
-    }
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      real w[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) w[c] = line(side, m, c);
-      project_adj(B, w, lQ[m], ll[side][m], lB);
-    }
-  }
-  make_basis_adj(wa, wb, k, lB, lwa, lwb);
-}
 
-// Reverse of normal_sweep: lcell[6][4] accumulates, la1/la2 receive the DF of cells f-1 / f
-// (the centre cells of the left / right reconstructions, DF branch only).
+// Normal sweep, one side.  cs[0..4]: the side's stencil, ordered away from the interface's far
+// side (side 0: cells f-3..f+1; side 1: cells f+2..f-2); (a_lo, a_c, a_hi) the DF of the stencil's
+// cells 1..3 in the same order; sgn_inv_dn = +1/dn (side 0) or -1/dn (side 1).  Gives the line
+// value w and its normal derivative wn.
 template <class real>
-DFW_HD void normal_sweep_adj(const real (*cell)[4], real a0, real a1, real a2, real a3, real inv_dn, const Coef<real>& k,
-                             const real* lwl, const real* lwr, const real* lwln, const real* lwrn, real (*lcell)[4],
-                             real& la1, real& la2) {
-  Basis<real> B = make_basis(cell[2], cell[3], k);
-  real Q[6][4];
+DFW_HD void normal_side(const Basis<real>& B, const real (*cs)[4], real a_lo, real a_c, real a_hi, real sgn_inv_dn,
+                        const Coef<real>& k, real* w, real* wn) {
+  real Q[5][4];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) project(B, cell[m], Q[m]);
-  real ql[4], qld[4], qr[4], qrd[4];
+  for (int m = 0; m < 5; ++m) project(B, cs[m], Q[m]);
+  real q[4], qd[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     real s[5], P2[2];
 #pragma unroll
     for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-    recon_poly<real, 2>(s, a0, a1, a2, k, P2);
-    ql[c] = P2[0];
-    qld[c] = P2[1] * inv_dn;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) s[m] = Q[5 - m][c];
-    recon_poly<real, 2>(s, a3, a2, a1, k, P2);
-    qr[c] = P2[0];
-    qrd[c] = -P2[1] * inv_dn;
+    recon_poly<real, 2>(s, a_lo, a_c, a_hi, k, P2);
+    q[c] = P2[0];
+    qd[c] = P2[1] * sgn_inv_dn;
   }
-  BasisAdj<real> lB;
-  lB.zero();
-  real lql[4] = {0, 0, 0, 0}, lqld[4] = {0, 0, 0, 0}, lqr[4] = {0, 0, 0, 0}, lqrd[4] = {0, 0, 0, 0};
-  unproject_adj(B, ql, lwl, lql, lB);
-  unproject_adj(B, qr, lwr, lqr, lB);
-  unproject_adj(B, qld, lwln, lqld, lB);
-  unproject_adj(B, qrd, lwrn, lqrd, lB);
-  real lQ[6][4];
+  unproject(B, q, w);
+  unproject(B, qd, wn);
+}
+
+// Reverse of normal_side; cell(m, c) gives component c of stencil cell m.  lcs[m] (the stencil
+// cells), the basis adjoint lB and la_c (the DF of the reconstructed cell, DF branch only)
+// accumulate.  One characteristic component at a time: its projection, reconstruction forward and
+// backward, and its share of the projection adjoints, so that only one chain is live.
+template <int C, class real, class CellFn>
+DFW_HD void normal_side_adj_comp(const Basis<real>& B, CellFn cell, real a_lo, real a_c, real a_hi, real sgn_inv_dn,
+                                 const Coef<real>& k, const real* lw, const real* lwn, real lqc, real lqdc,
+                                 real (*lcs)[4], BasisAdj<real>& lB, real& la_c) {
+  real s[5], P2[2], lP[2], lQc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-  for (int m = 0; m < 6; ++m)
+  for (int m = 0; m < 5; ++m) {
+    real w[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) lQ[m][c] = real(0);
+    for (int c = 0; c < 4; ++c) w[c] = cell(m, c);
+    s[m] = project_comp<C>(B, w);
+  }
+  lP[0] = lqc;
+  lP[1] = lqdc * sgn_inv_dn;
+  recon_poly_adj<real, 2>(s, a_lo, a_c, a_hi, k, lP, lQc, la_c, P2);
+  unproject_adj_B_comp<C>(B, P2[0], lw, lB);
+  unproject_adj_B_comp<C>(B, P2[1] * sgn_inv_dn, lwn, lB);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    real w[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = cell(m, c);
+    project_adj_comp<C>(B, w, lQc[m], lcs[m], lB);
+  }
+}
+
+// cell(m, c) is read once per component; callers that keep the cells in memory pass a reader that
+// reloads them, so that nothing but the accumulators lives from one component to the next.
+template <class real, class CellFn>
+DFW_HD void normal_side_adj(const Basis<real>& B, CellFn cell, real a_lo, real a_c, real a_hi, real sgn_inv_dn,
+                            const Coef<real>& k, const real* lw, const real* lwn, real (*lcs)[4], BasisAdj<real>& lB,
+                            real& la_c) {
+  normal_side_adj_comp<0>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<0>(B, lw),
+                          unproject_adj_q_comp<0>(B, lwn), lcs, lB, la_c);
+  normal_side_adj_comp<1>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<1>(B, lw),
+                          unproject_adj_q_comp<1>(B, lwn), lcs, lB, la_c);
+  normal_side_adj_comp<2>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<2>(B, lw),
+                          unproject_adj_q_comp<2>(B, lwn), lcs, lB, la_c);
+  normal_side_adj_comp<3>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<3>(B, lw),
+                          unproject_adj_q_comp<3>(B, lwn), lcs, lB, la_c);
+}
+
+// Segment, one side: line(m, c) = component c of the side's line value on segment row m-2;
+// al = DF of the side's cell on rows -1, 0, +1.  Gives the states and their tangential derivatives
+// at the two Gauss points (as segment_fluxes computes them).
+template <class real, class LineFn>
+DFW_HD void segment_side(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
+                         real (*gw)[4], real (*gwt)[4]) {
+  real Q[5][4];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    real w[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = line(m, c);
+    project(B, w, Q[m]);
+  }
+  real qv[2][4], qd[2][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    real s[5], lP[2], lQc[5];
+    real s[5], Pc[5];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      s[m] = Q[m][c];
-      lQc[m] = real(0);
-    }
-    lP[0] = lql[c];
-    lP[1] = lqld[c] * inv_dn;
-    recon_poly_adj<real, 2>(s, a0, a1, a2, k, lP, lQc, la1);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      lQ[m][c] += lQc[m];
-      s[m] = Q[5 - m][c];
-      lQc[m] = real(0);
-    }
-    lP[0] = lqr[c];
-    lP[1] = -lqrd[c] * inv_dn;
-    recon_poly_adj<real, 2>(s, a3, a2, a1, k, lP, lQc, la2);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) lQ[5 - m][c] += lQc[m];
+    for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
+    recon_poly<real, 5>(s, al[0], al[1], al[2], k, Pc);
+    real v0, d0, v1, d1;
+    eval_poly_at(Pc, real(kXiGp0), v0, d0);
+    eval_poly_at(Pc, real(kXiGp1), v1, d1);
+    qv[0][c] = v0;
+    qv[1][c] = v1;
+    qd[0][c] = d0 * inv_dt;
+    qd[1][c] = d1 * inv_dt;
   }
 #pragma unroll
-  for (int m = 0; m < 6; ++m) project_adj(B, cell[m], lQ[m], lcell[m], lB);
-  make_basis_adj(cell[2], cell[3], k, lB, lcell[2], lcell[3]);
+  for (int g = 0; g < 2; ++g) {
+    unproject(B, qv[g], gw[g]);
+    unproject(B, qd[g], gwt[g]);
+  }
+}
+
+// Reverse of segment_side for the adjoints lgw, lgwt of the Gauss-point states: ll[m] (the side's
+// line values), lB and la_c accumulate.  One characteristic component at a time, as in
+// normal_side_adj.
+template <int C, class real, class LineFn>
+DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
+                                  const real (*lgw)[4], const real (*lgwt)[4], real lqv0, real lqv1, real lqd0,
+                                  real lqd1, real (*ll)[4], BasisAdj<real>& lB, real& la_c) {
+  real s[5], Pc[5], lP[5] = {0, 0, 0, 0, 0}, lQc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    real w[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = line(m, c);
+    s[m] = project_comp<C>(B, w);
+  }
+  eval_poly_at_adj(real(kXiGp0), lqv0, lqd0 * inv_dt, lP);
+  eval_poly_at_adj(real(kXiGp1), lqv1, lqd1 * inv_dt, lP);
+  recon_poly_adj<real, 5>(s, al[0], al[1], al[2], k, lP, lQc, la_c, Pc);
+  real v0, d0, v1, d1;
+  eval_poly_at(Pc, real(kXiGp0), v0, d0);
+  eval_poly_at(Pc, real(kXiGp1), v1, d1);
+  unproject_adj_B_comp<C>(B, v0, lgw[0], lB);
+  unproject_adj_B_comp<C>(B, v1, lgw[1], lB);
+  unproject_adj_B_comp<C>(B, d0 * inv_dt, lgwt[0], lB);
+  unproject_adj_B_comp<C>(B, d1 * inv_dt, lgwt[1], lB);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    real w[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = line(m, c);
+    project_adj_comp<C>(B, w, lQc[m], ll[m], lB);
+  }
+}
+
+template <class real, class LineFn>
+DFW_HD void segment_side_adj(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
+                             const real (*lgw)[4], const real (*lgwt)[4], real (*ll)[4], BasisAdj<real>& lB,
+                             real& la_c) {
+#define DFW_SEG_COMP(C)                                                                                          \
+  segment_side_adj_comp<C>(B, line, al, inv_dt, k, lgw, lgwt, unproject_adj_q_comp<C>(B, lgw[0]),              \
+                           unproject_adj_q_comp<C>(B, lgw[1]), unproject_adj_q_comp<C>(B, lgwt[0]),            \
+                           unproject_adj_q_comp<C>(B, lgwt[1]), ll, lB, la_c)
+  DFW_SEG_COMP(0);
+  DFW_SEG_COMP(1);
+  DFW_SEG_COMP(2);
+  DFW_SEG_COMP(3);
+#undef DFW_SEG_COMP
+}
+
+// Reverse of the flux, its time derivative and the DF at one Gauss point (left state wl with normal
+// and tangential derivatives wln, wlt; right state likewise): lF, lFt are the adjoints of the
+// Gauss point's flux and time derivative, ldf that of its DF value.  Outputs accumulate.
+template <class real, int FLUX>
+DFW_HD void gp_flux_adj(const real* wl, const real* wln, const real* wlt, const real* wr, const real* wrn,
+                        const real* wrt, real dt, const Coef<real>& k, const real* lF, const real* lFt, real ldf,
+                        real* lwl, real* lwln, real* lwlt, real* lwr, real* lwrn, real* lwrt) {
+  const Prim<real> ql = prim(wl, k), qr = prim(wr, k);
+  PrimAdj<real> lql, lqr;
+  lql.zero();
+  lqr.zero();
+  if (FLUX == 0)
+    lf_flux_adj(wl, wln, wlt, wr, wrn, wrt, ql, qr, k, lF, lFt, lwl, lwln, lwlt, lwr, lwrn, lwrt, lql, lqr);
+  else
+    gks_flux_adj(wl, wln, wlt, wr, wrn, wrt, ql, qr, dt, k, lF, lFt, lwl, lwln, lwlt, lwr, lwrn, lwrt, lql, lqr);
+  df_factor_adj(ql, qr, ldf, lql, lqr);
+  prim_adj(wl, ql, k, lql, lwl);
+  prim_adj(wr, qr, k, lqr, lwr);
 }
 
 }  // namespace dfw

@@ -26,18 +26,26 @@ constexpr int kAdjSlots = 26;  // 6 stencil cells x 4 components, then the DF of
 
 template <int TF, int TR>
 struct AdjTile {
-  static constexpr int NR = TR + 4;   // segment rows = threads per interface column
-  static constexpr int NT = TF * NR;  // threads per workgroup
+  static constexpr int NR = TR + 4;   // segment rows of the tile
+  static constexpr int NP = TF * NR;  // interface segments = lane pairs
+  static constexpr int NT = 2 * NP;   // threads: one per segment side
   static constexpr int NQ = TR + 8;   // normal-sweep rows
   static constexpr int WN = TF + 5;   // cells along the normal
   static constexpr int AN = TF + 3;   // alpha cells along the normal
 };
 
+// Value of the other lane of the pair (lanes 2p and 2p+1 hold the two sides of one segment).
+template <class real>
+__device__ __forceinline__ real pair_swap(real x) {
+  return __shfl_xor(x, 1);
+}
+
 // STAGE 1: seeds lam_L = dt/2 P + dt Q, lam_Lt = dt^2/8 P + dt^2/6 Q (P = adjoint of W*, Q = of R).
 // STAGE 2: seeds lam_Lt = dt^2/3 P (P = adjoint of W^{n+1}) and the adjoint LA of alpha^{n+1}, with
 //          the stage's interface DF products DX, DY.
+// Thread 2p + s works on side s of interface segment p (s = 0: the cell before the interface).
 template <class real, int FLUX, int STAGE, int TF, int TR>
-__global__ __launch_bounds__(TF * (TR + 4)) void k_adj_faces(
+__global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
     const real* __restrict__ W, const real* __restrict__ alpha, const real* __restrict__ P,
     const real* __restrict__ Q, const real* __restrict__ LA, const real* __restrict__ DX,
     const real* __restrict__ DY, real* __restrict__ BX, real* __restrict__ BY, GridDesc G, Scheme S,
@@ -46,6 +54,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_adj_faces(
   __shared__ real sW[4][T::NQ][T::WN];
   __shared__ real sA[T::NQ][T::AN];
   __shared__ real sL[8][TF * T::NQ];
+  __shared__ real sX[4][T::NT];
 
   int b = blockIdx.x;
   const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
@@ -93,63 +102,82 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_adj_faces(
   }
   __syncthreads();
 
+  const int side = tid & 1, pr = tid >> 1;
   int fl, rr;
   if (dir == 0) {
-    fl = tid % TF;
-    rr = tid / TF;
+    fl = pr % TF;
+    rr = pr / TF;
   } else {
-    rr = tid % T::NR;
-    fl = tid / T::NR;
+    rr = pr % T::NR;
+    fl = pr / T::NR;
   }
   auto lidx = [&](int q, int c) { return dir == 0 ? q * TF + c : c * T::NQ + q; };
-  auto tidx = [&](int c, int r) { return dir == 0 ? r * TF + c : c * T::NR + r; };
+  auto pidx = [&](int c, int r) { return dir == 0 ? r * TF + c : c * T::NR + r; };
   const int f = f0 + fl;
-  const int t = t0 - 2 + rr;  // segment row of this thread
+  const int t = t0 - 2 + rr;  // segment row of this pair
   const bool face = f <= Nn;
+  const real sgn_dn = side ? -inv_dn : inv_dn;
 
-  // ---- normal sweep (forward) of the rows the segments read: own row q = rr+2, and four extra
-  //      rows (q = 0, 1, TR+6, TR+7) on the threads with rr < 4
-  real wln[4] = {0, 0, 0, 0}, wrn[4] = {0, 0, 0, 0};
-  auto ns_row = [&](int q, real* dl, real* dr) {
-    real cell[6][4];
+  // this side's normal stencil on sweep row q (cells ordered away from the far side) and the DF
+  // of its cells 1..3
+  auto stencil = [&](int q, real(*cs)[4]) {
 #pragma unroll
-    for (int m = 0; m < 6; ++m)
+    for (int m = 0; m < 5; ++m)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][q][fl + m];
-    real wl[4], wr[4];
-    normal_sweep<real>(cell, sA[q][fl], sA[q][fl + 1], sA[q][fl + 2], sA[q][fl + 3], inv_dn, k, wl, wr, dl, dr);
+      for (int c = 0; c < 4; ++c) cs[m][c] = sW[c][q][fl + (side ? 5 - m : m)];
+  };
+  auto a_of = [&](int q, int m) { return sA[q][fl + (side ? 3 - m : m)]; };  // stencil cell m+1
+  auto basis_row = [&](int q) {
+    real wa[4], wb[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      sL[c][lidx(q, fl)] = wl[c];
-      sL[4 + c][lidx(q, fl)] = wr[c];
+      wa[c] = sW[c][q][fl + 2];
+      wb[c] = sW[c][q][fl + 3];
     }
+    return make_basis(wa, wb, k);
   };
   auto row_needed = [&](int q) {
     const int tq = t0 - 4 + q;
     return face && tq >= -2 && tq <= Nt + 1;
   };
-  if (row_needed(rr + 2)) ns_row(rr + 2, wln, wrn);
+
+  // ---- normal sweep (forward), this side: own row q = rr+2, and four extra rows
+  //      (q = 0, 1, TR+6, TR+7) on the pairs with rr < 4
+  real wn[4] = {0, 0, 0, 0};
+  auto ns_row = [&](int q, real* dn) {
+    const Basis<real> B = basis_row(q);
+    real cs[5][4], w[4];
+    stencil(q, cs);
+    normal_side<real>(B, cs, a_of(q, 0), a_of(q, 1), a_of(q, 2), sgn_dn, k, w, dn);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sL[4 * side + c][lidx(q, fl)] = w[c];
+  };
+  if (row_needed(rr + 2)) ns_row(rr + 2, wn);
   if (rr < 4) {
     const int q2 = rr < 2 ? rr : rr + TR + 4;
-    real dl[4], dr[4];
-    if (row_needed(q2)) ns_row(q2, dl, dr);
+    real d[4];
+    if (row_needed(q2)) ns_row(q2, d);
   }
   __syncthreads();
 
-  // ---- segment adjoint
+  // ---- segment forward, this side: states at the two Gauss points
   const bool seg = face && t >= 0 && t < Nt;
-  real lwa[4] = {0, 0, 0, 0}, lwb[4] = {0, 0, 0, 0}, lwln[4] = {0, 0, 0, 0}, lwrn[4] = {0, 0, 0, 0};
-  real ll[2][5][4];
+  const Basis<real> B = basis_row(rr + 2);
+  real al[3];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int q = 0; q < 3; ++q) al[q] = sA[rr + 1 + q][fl + 1 + side];
+  auto line = [&](int m, int c) -> real { return sL[4 * side + c][lidx(rr + m, fl)]; };
+  real gw[2][4], gwt[2][4];
 #pragma unroll
-    for (int m = 0; m < 5; ++m)
+  for (int g = 0; g < 2; ++g)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) ll[s][m][c] = real(0);
-  real la_c[2] = {0, 0};
+    for (int c = 0; c < 4; ++c) gw[g][c] = gwt[g][c] = real(0);
+  if (seg) segment_side(B, line, al, inv_dt, k, gw, gwt);
+
+  // ---- adjoints of the face sums from the cell seeds (face f: -1/dn to cell f-1, +1/dn to cell f)
   const int cmap[4] = {0, dir ? 2 : 1, dir ? 1 : 2, 3};
+  real lFs[4] = {0, 0, 0, 0}, lFts[4] = {0, 0, 0, 0}, ldfp = real(0);
   if (seg) {
-    // adjoints of the face sums from the cell seeds (face f: -1/dn to cell f-1, +1/dn to cell f)
     const bool has_a = f >= 1, has_b = f < Nn;
     const size_t ga = dir == 0 ? (size_t)t * nx + (f - 1) : (size_t)(f - 1) * nx + t;
     const size_t gb = dir == 0 ? (size_t)t * nx + f : (size_t)f * nx + t;
@@ -182,14 +210,16 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_adj_faces(
         lFt[gc] = (Ltb - Lta) * inv_dn;
       }
     }
-    real lFs[4], lFts[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      lFs[c] = real(0.5) * lF[cmap[c]];
-      lFts[c] = real(0.5) * lFt[cmap[c]];
-    }
+    // local component order (normal momentum first), quadrature weight 1/2
+    lFs[0] = real(0.5) * lF[0];
+    lFs[1] = real(0.5) * (dir ? lF[2] : lF[1]);
+    lFs[2] = real(0.5) * (dir ? lF[1] : lF[2]);
+    lFs[3] = real(0.5) * lF[3];
+    lFts[0] = real(0.5) * lFt[0];
+    lFts[1] = real(0.5) * (dir ? lFt[2] : lFt[1]);
+    lFts[2] = real(0.5) * (dir ? lFt[1] : lFt[2]);
+    lFts[3] = real(0.5) * lFt[3];
     // adjoint of the Gauss-point DF product: alpha_new of a cell is the product of its four faces
-    real ldfp = real(0);
     if (STAGE == 2) {
       const size_t rx = (size_t)nx + 1;
       if (dir == 0) {
@@ -214,61 +244,140 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_adj_faces(
         }
       }
     }
+  }
+
+  // ---- Gauss point g = side: both sides' states (the partner's over a lane swap), flux and DF
+  //      adjoint there; then each side collects its own state adjoints at both points
+  real wl[4], wr[4], wlt[4], wrt[4], wln[4], wrn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const real mine = side ? gw[1][c] : gw[0][c], mine_t = side ? gwt[1][c] : gwt[0][c];
+    const real other = pair_swap(side ? gw[0][c] : gw[1][c]);  // partner's state at my point
+    const real other_t = pair_swap(side ? gwt[0][c] : gwt[1][c]);
+    const real other_n = pair_swap(wn[c]);
+    wl[c] = side ? other : mine;
+    wr[c] = side ? mine : other;
+    wlt[c] = side ? other_t : mine_t;
+    wrt[c] = side ? mine_t : other_t;
+    wln[c] = side ? other_n : wn[c];
+    wrn[c] = side ? wn[c] : other_n;
+  }
+  real dfo = real(1);
+  if (STAGE == 2 && seg) dfo = df_factor(prim(wl, k), prim(wr, k));
+  const real df_other = pair_swap(dfo);
+  real lwl[4] = {0, 0, 0, 0}, lwln[4] = {0, 0, 0, 0}, lwlt[4] = {0, 0, 0, 0};
+  real lwr[4] = {0, 0, 0, 0}, lwrn[4] = {0, 0, 0, 0}, lwrt[4] = {0, 0, 0, 0};
+  if (seg)
+    gp_flux_adj<real, FLUX>(wl, wln, wlt, wr, wrn, wrt, dt, k, lFs, lFts, STAGE == 2 ? ldfp * df_other : real(0), lwl,
+                            lwln, lwlt, lwr, lwrn, lwrt);
+  real lgw[2][4], lgwt[2][4], lwn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const real own = side ? lwr[c] : lwl[c], own_t = side ? lwrt[c] : lwlt[c], own_n = side ? lwrn[c] : lwln[c];
+    const real got = pair_swap(side ? lwl[c] : lwr[c]);  // my side's adjoint at the partner's point
+    const real got_t = pair_swap(side ? lwlt[c] : lwrt[c]);
+    const real got_n = pair_swap(side ? lwln[c] : lwrn[c]);
+    lgw[0][c] = side ? got : own;
+    lgw[1][c] = side ? own : got;
+    lgwt[0][c] = side ? got_t : own_t;
+    lgwt[1][c] = side ? own_t : got_t;
+    lwn[c] = side ? got_n + own_n : own_n + got_n;  // Gauss point 0 first on both lanes
+  }
+  __syncthreads();  // the reverse reloads its LDS inputs after this point
+
+  // ---- segment reverse, this side: characteristic line adjoints, then the line adjoints of the
+  //      five rows each segment reads, summed per row through LDS in a fixed order
+  BasisAdj<real> lB;
+  lB.zero();
+  real ll[5][4];
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ll[m][c] = real(0);
+  real la_seg = real(0);
+  if (seg) segment_side_adj(B, line, al, inv_dt, k, lgw, lgwt, ll, lB, la_seg);
+  real acc[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sX[c][tid] = ll[m][c];
+    __syncthreads();
+    const int src = rr + 2 - m;  // the segment whose line m is this pair's row
+    if (src >= 0 && src < T::NR) {
+      const int st = 2 * pidx(fl, src) + side;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += sX[c][st];
+    }
+    __syncthreads();
+  }
+
+  // ---- normal-sweep adjoint of the rows this tile owns: its TR rows, the two ghost rows below the
+  //      grid (first tile) and the two above it (tile of the last row)
+  const bool own = face && ((rr >= 2 && rr < TR + 2 && t < Nt) || (t0 == 0 && t < 0) ||
+                            (t >= Nt && t <= Nt + 1 && t0 + TR >= Nt));
+  real lcs[5][4];
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lcs[m][c] = real(0);
+  real la_ns = real(0);
+  if (own) {
+    auto cell = [&](int m, int c) -> real { return sW[c][rr + 2][fl + (side ? 5 - m : m)]; };
+    normal_side_adj<real>(B, cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc, lwn, lcs, lB,
+                          la_ns);
+  }
+  // basis adjoint of the pair (side 0 first on both lanes), then the two cells it is built from
+  BasisAdj<real> lBt;
+  {
+    BasisAdj<real> o;
+    o.u = pair_swap(lB.u);
+    o.v = pair_swap(lB.v);
+    o.c = pair_swap(lB.c);
+    o.ic = pair_swap(lB.ic);
+    o.H = pair_swap(lB.H);
+    o.hq2 = pair_swap(lB.hq2);
+    o.b1 = pair_swap(lB.b1);
+    o.b2 = pair_swap(lB.b2);
+    if (side) {
+      lBt = o;
+      basis_adj_add(lBt, lB);
+    } else {
+      lBt = lB;
+      basis_adj_add(lBt, o);
+    }
+  }
+  // cells f-2+... : side 0 holds stencil cells 0..4 (lcs[m] = cell m), side 1 cells 5..1
+  // (lcs[m] = cell 5-m).  Lane 0 writes cells 0, 1, 2 and the DF of cell f-1; lane 1 cells 3, 4, 5
+  // and the DF of cell f.  Each lane needs the partner's lcs[3] and lcs[4].
+  real r3[4], r4[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    r3[c] = pair_swap(lcs[3][c]);
+    r4[c] = pair_swap(lcs[4][c]);
+  }
+  if (!own) return;
+  real lbc[4] = {0, 0, 0, 0}, lbc2[4] = {0, 0, 0, 0};
+  {
     real wa[4], wb[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       wa[c] = sW[c][rr + 2][fl + 2];
       wb[c] = sW[c][rr + 2][fl + 3];
     }
-    real al[2][3];
-#pragma unroll
-    for (int side = 0; side < 2; ++side)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) al[side][q] = sA[rr + 1 + q][fl + 1 + side];
-    auto line = [&](int side, int m, int c) -> real { return sL[4 * side + c][lidx(rr + m, fl)]; };
-    segment_fluxes_adj<real, FLUX>(wa, wb, line, al, wln, wrn, dt, inv_dt, k, lFs, lFts, ldfp, lwa, lwb, ll, lwln,
-                                   lwrn, la_c);
+    make_basis_adj(wa, wb, k, lBt, lbc, lbc2);  // the same adjoint reaches both cells
   }
-  __syncthreads();
-
-  // ---- line adjoints of each row: the five segments t+2-m (m = 0..4) that read it, in order of m
-  real acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sL[q][tid] = ll[q >> 2][m][q & 3];
-    __syncthreads();
-    const int src = rr + 2 - m;
-    if (src >= 0 && src < T::NR) {
-      const int st = tidx(fl, src);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] += sL[q][st];
-    }
-    __syncthreads();
-  }
-
-  // ---- normal-sweep adjoint of the rows this tile owns: its TR rows, the two ghost rows below
-  //      the grid (first tile) and the two above it (tile of the last row)
-  const bool own = face && ((rr >= 2 && rr < TR + 2 && t < Nt) || (t0 == 0 && t < 0) ||
-                            (t >= Nt && t <= Nt + 1 && t0 + TR >= Nt));
-  if (!own) return;
-  real cell[6][4];
-#pragma unroll
-  for (int m = 0; m < 6; ++m)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][rr + 2][fl + m];
-  real lcell[6][4];
-#pragma unroll
-  for (int m = 0; m < 6; ++m)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) lcell[m][c] = real(0);
-  real la1 = la_c[0], la2 = la_c[1];
-  normal_sweep_adj<real>(cell, sA[rr + 2][fl], sA[rr + 2][fl + 1], sA[rr + 2][fl + 2], sA[rr + 2][fl + 3], inv_dn, k,
-                         acc, acc + 4, lwln, lwrn, lcell, la1, la2);
+  real out[3][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    lcell[2][c] += lwa[c];
-    lcell[3][c] += lwb[c];
+    if (side == 0) {
+      out[0][c] = lcs[0][c];
+      out[1][c] = lcs[1][c] + r4[c];
+      out[2][c] = (lcs[2][c] + r3[c]) + lbc[c];
+    } else {
+      out[0][c] = (r3[c] + lcs[2][c]) + lbc[c];
+      out[1][c] = r4[c] + lcs[1][c];
+      out[2][c] = lcs[0][c];
+    }
   }
   size_t sB;
   real* o;
@@ -279,12 +388,12 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_adj_faces(
     sB = (size_t)(ny + 1) * (nx + 4);
     o = BY + (size_t)f * (nx + 4) + (t + 2);
   }
+  const int m0 = 3 * side;
 #pragma unroll
-  for (int m = 0; m < 6; ++m)
+  for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) o[(m * 4 + cmap[c]) * sB] = lcell[m][c];
-  o[24 * sB] = la1;
-  o[25 * sB] = la2;
+    for (int c = 0; c < 4; ++c) o[((m0 + m) * 4 + cmap[c]) * sB] = out[m][c];
+  o[(24 + side) * sB] = la_seg + la_ns;
 }
 
 // Indices in [lo, hi] that the boundary map sends to cell n of a line of Nn cells: a contiguous
@@ -372,7 +481,7 @@ struct AdjShape {
   int tf, tr;
 };
 // Interface tiles of the adjoint kernel, per flux (LF, GKS).
-static constexpr AdjShape kAdjShapes[2] = {{16, 28}, {16, 12}};
+static constexpr AdjShape kAdjShapes[2] = {{8, 28}, {8, 12}};
 
 static int adj_tiles(int flux, int nx, int ny) {
   const AdjShape s = kAdjShapes[flux];
@@ -384,7 +493,8 @@ static void launch_adj_faces(const real* W, const real* A, const real* P, const 
                              const real* DX, const real* DY, real* BX, real* BY, const GridDesc& G, const Scheme& S,
                              const double* dt_hist, int step, hipStream_t st) {
   constexpr int TF = kAdjShapes[FLUX].tf, TR = kAdjShapes[FLUX].tr;
-  hipLaunchKernelGGL((k_adj_faces<real, FLUX, STAGE, TF, TR>), dim3(adj_tiles(FLUX, G.nx, G.ny)), dim3(TF * (TR + 4)),
+  hipLaunchKernelGGL((k_adj_faces<real, FLUX, STAGE, TF, TR>), dim3(adj_tiles(FLUX, G.nx, G.ny)),
+                     dim3(2 * TF * (TR + 4)),
                      0, st, W, A, P, Q, LA, DX, DY, BX, BY, G, S, dt_hist, step);
 }
 

@@ -177,7 +177,8 @@ int main() {
         check(flux ? (taumode ? "gks_flux_tau0" : "gks_flux") : "lf_flux", x, 8, f, a);
       }
     }
-    // ---- normal sweep: 6 cells (24) + 4 alphas -> wl, wr, wln, wrn (16)
+    // ---- normal sweep: 6 cells (24) + 4 alphas -> wl, wr, wln, wrn (16).  The adjoint is composed
+    //      from the two one-side pieces and the basis adjoint, as the interface kernel composes it.
     for (int branch = 0; branch < 2; ++branch) {
       std::vector<double> x(28);
       for (int m = 0; m < 6; ++m) rand_state(&x[4 * m], 0.5);
@@ -190,19 +191,52 @@ int main() {
         normal_sweep<real>(cell, xx[24], xx[25], xx[26], xx[27], idn, k, y, y + 4, y + 8, y + 12);
       };
       auto a = [&](const double* xx, const double* l, double* lx) {
-        real cell[6][4], lcell[6][4] = {};
-        for (int m = 0; m < 6; ++m)
-          for (int c = 0; c < 4; ++c) cell[m][c] = xx[4 * m + c];
+        real cs0[5][4], cs1[5][4], lcs0[5][4] = {}, lcs1[5][4] = {};
+        for (int m = 0; m < 5; ++m)
+          for (int c = 0; c < 4; ++c) {
+            cs0[m][c] = xx[4 * m + c];
+            cs1[m][c] = xx[4 * (5 - m) + c];
+          }
+        Basis<real> B = make_basis(xx + 8, xx + 12, k);
+        BasisAdj<real> lB;
+        lB.zero();
         real la1 = 0, la2 = 0;
-        normal_sweep_adj<real>(cell, xx[24], xx[25], xx[26], xx[27], idn, k, l, l + 4, l + 8, l + 12, lcell, la1, la2);
-        for (int m = 0; m < 6; ++m)
-          for (int c = 0; c < 4; ++c) lx[4 * m + c] += lcell[m][c];
+        auto c0 = [&](int m, int c) -> real { return cs0[m][c]; };
+        auto c1 = [&](int m, int c) -> real { return cs1[m][c]; };
+        normal_side_adj<real>(B, c0, xx[24], xx[25], xx[26], idn, k, l, l + 8, lcs0, lB, la1);
+        normal_side_adj<real>(B, c1, xx[27], xx[26], xx[25], -idn, k, l + 4, l + 12, lcs1, lB, la2);
+        for (int m = 0; m < 5; ++m)
+          for (int c = 0; c < 4; ++c) {
+            lx[4 * m + c] += lcs0[m][c];
+            lx[4 * (5 - m) + c] += lcs1[m][c];
+          }
+        make_basis_adj(xx + 8, xx + 12, k, lB, lx + 8, lx + 12);
         lx[25] += la1;
         lx[26] += la2;
       };
       check(branch ? "normal_sweep_df" : "normal_sweep", x, 16, f, a);
+      // the one-side forward pieces reproduce the whole sweep
+      {
+        real y[16], cell[6][4], cs0[5][4], cs1[5][4], w[16];
+        for (int m = 0; m < 6; ++m)
+          for (int c = 0; c < 4; ++c) cell[m][c] = x[4 * m + c];
+        for (int m = 0; m < 5; ++m)
+          for (int c = 0; c < 4; ++c) {
+            cs0[m][c] = cell[m][c];
+            cs1[m][c] = cell[5 - m][c];
+          }
+        normal_sweep<real>(cell, x[24], x[25], x[26], x[27], idn, k, y, y + 4, y + 8, y + 12);
+        Basis<real> B = make_basis(cell[2], cell[3], k);
+        normal_side<real>(B, cs0, x[24], x[25], x[26], idn, k, w, w + 8);
+        normal_side<real>(B, cs1, x[27], x[26], x[25], -idn, k, w + 4, w + 12);
+        double d = 0;
+        for (int i = 0; i < 16; ++i) d = std::max(d, std::fabs(w[i] - y[i]) / (std::fabs(y[i]) + 1e-300));
+        std::printf("%s %.3e\n", branch ? "normal_side_fwd_df" : "normal_side_fwd", d);
+      }
     }
-    // ---- segment: wa, wb (8), lines 2x5x4 (40), wln, wrn (8), centre alphas (2) -> Fs, Fts, dfp (9)
+    // ---- segment: wa, wb (8), lines 2x5x4 (40), wln, wrn (8), centre alphas (2) -> Fs, Fts, dfp (9).
+    //      Adjoint composed from the one-side pieces, the per-Gauss-point flux adjoint and the basis
+    //      adjoint, as the interface kernel composes it.
     for (int flux = 0; flux < 2; ++flux)
       for (int branch = 0; branch < 2; ++branch) {
         std::vector<double> x(58);
@@ -214,28 +248,51 @@ int main() {
         x[56] = branch ? 0.3 : 1.0;
         x[57] = branch ? 0.2 : 1.0;
         const real dt = 2e-3, idt = 40.0;
+        auto alphas = [&](const double* xx, real (*al)[3]) {
+          const real a[2][3] = {{branch ? 0.1 : 1.0, xx[56], 0.2}, {0.3, xx[57], branch ? 0.4 : 1.0}};
+          for (int s = 0; s < 2; ++s)
+            for (int q = 0; q < 3; ++q) al[s][q] = a[s][q];
+        };
         auto run = [&](const double* xx, double* y) {
           auto line = [&](int side, int m, int c) -> real { return xx[8 + 20 * side + 4 * m + c]; };
-          real al[2][3] = {{branch ? 0.1 : 1.0, xx[56], 0.2}, {0.3, xx[57], branch ? 0.4 : 1.0}};
+          real al[2][3];
+          alphas(xx, al);
           real dfp;
           if (flux == 0) segment_fluxes<real, 0, true, true>(xx, xx + 4, line, al, xx + 48, xx + 52, dt, idt, k, y, y + 4, dfp);
           else segment_fluxes<real, 1, true, true>(xx, xx + 4, line, al, xx + 48, xx + 52, dt, idt, k, y, y + 4, dfp);
           y[8] = dfp;
         };
         auto a = [&](const double* xx, const double* l, double* lx) {
-          auto line = [&](int side, int m, int c) -> real { return xx[8 + 20 * side + 4 * m + c]; };
-          real al[2][3] = {{branch ? 0.1 : 1.0, xx[56], 0.2}, {0.3, xx[57], branch ? 0.4 : 1.0}};
-          real ll[2][5][4] = {};
+          real al[2][3];
+          alphas(xx, al);
+          Basis<real> B = make_basis(xx, xx + 4, k);
+          real gw[2][2][4], gwt[2][2][4];
+          for (int s = 0; s < 2; ++s) {
+            auto line = [&](int m, int c) -> real { return xx[8 + 20 * s + 4 * m + c]; };
+            segment_side(B, line, al[s], idt, k, gw[s], gwt[s]);
+          }
+          real dfg[2];
+          for (int g = 0; g < 2; ++g) dfg[g] = df_factor(prim(gw[0][g], k), prim(gw[1][g], k));
+          real lgw[2][2][4] = {}, lgwt[2][2][4] = {};
+          for (int g = 0; g < 2; ++g) {
+            if (flux == 0)
+              gp_flux_adj<real, 0>(gw[0][g], xx + 48, gwt[0][g], gw[1][g], xx + 52, gwt[1][g], dt, k, l, l + 4,
+                                   l[8] * dfg[1 - g], lgw[0][g], lx + 48, lgwt[0][g], lgw[1][g], lx + 52, lgwt[1][g]);
+            else
+              gp_flux_adj<real, 1>(gw[0][g], xx + 48, gwt[0][g], gw[1][g], xx + 52, gwt[1][g], dt, k, l, l + 4,
+                                   l[8] * dfg[1 - g], lgw[0][g], lx + 48, lgwt[0][g], lgw[1][g], lx + 52, lgwt[1][g]);
+          }
+          BasisAdj<real> lB;
+          lB.zero();
           real lac[2] = {0, 0};
-          if (flux == 0)
-            segment_fluxes_adj<real, 0>(xx, xx + 4, line, al, xx + 48, xx + 52, dt, idt, k, l, l + 4, l[8], lx, lx + 4, ll,
-                                        lx + 48, lx + 52, lac);
-          else
-            segment_fluxes_adj<real, 1>(xx, xx + 4, line, al, xx + 48, xx + 52, dt, idt, k, l, l + 4, l[8], lx, lx + 4, ll,
-                                        lx + 48, lx + 52, lac);
-          for (int s = 0; s < 2; ++s)
+          for (int s = 0; s < 2; ++s) {
+            auto line = [&](int m, int c) -> real { return xx[8 + 20 * s + 4 * m + c]; };
+            real ll[5][4] = {};
+            segment_side_adj(B, line, al[s], idt, k, lgw[s], lgwt[s], ll, lB, lac[s]);
             for (int m = 0; m < 5; ++m)
-              for (int c = 0; c < 4; ++c) lx[8 + 20 * s + 4 * m + c] += ll[s][m][c];
+              for (int c = 0; c < 4; ++c) lx[8 + 20 * s + 4 * m + c] += ll[m][c];
+          }
+          make_basis_adj(xx, xx + 4, k, lB, lx, lx + 4);
           lx[56] += lac[0];
           lx[57] += lac[1];
         };

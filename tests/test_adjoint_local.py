@@ -25,7 +25,7 @@ def test_every_adjoint_matches_central_differences(lines):
     names = {ln[0] for ln in lines}
     for need in ("project", "unproject", "recon5_weno", "recon5_df", "recon2_weno", "recon2_df", "df_factor",
                  "lf_flux", "gks_flux", "gks_flux_tau0", "normal_sweep", "normal_sweep_df", "segment_lf",
-                 "segment_lf_df", "segment_gks", "segment_gks_df"):
+                 "segment_lf_df", "segment_gks", "segment_gks_df", "normal_side_fwd", "normal_side_fwd_df"):
         assert need in names, need
     worst = max(lines, key=lambda ln: float(ln[1]))
     assert float(worst[1]) < 1e-6, worst
