@@ -1041,14 +1041,14 @@ DFW_HD void normal_side(const Basis<real>& B, const real (*cs)[4], real a_lo, re
   unproject(B, qd, wn);
 }
 
-// Reverse of normal_side; cell(m, c) gives component c of stencil cell m.  lcs[m] (the stencil
-// cells), the basis adjoint lB and la_c (the DF of the reconstructed cell, DF branch only)
-// accumulate.  One characteristic component at a time: its projection, reconstruction forward and
+// Reverse of normal_side; cell(m, c) gives component c of stencil cell m.  The stencil cells'
+// adjoints go to lc_add(m, c, v) (add v to cell m, component c); the basis adjoint lB and la_c (the
+// DF of the reconstructed cell, DF branch only) accumulate.  One characteristic component at a time: its projection, reconstruction forward and
 // backward, and its share of the projection adjoints, so that only one chain is live.
-template <int C, class real, class CellFn>
+template <int C, class real, class CellFn, class AddFn>
 DFW_HD void normal_side_adj_comp(const Basis<real>& B, CellFn cell, real a_lo, real a_c, real a_hi, real sgn_inv_dn,
                                  const Coef<real>& k, const real* lw, const real* lwn, real lqc, real lqdc,
-                                 real (*lcs)[4], BasisAdj<real>& lB, real& la_c) {
+                                 AddFn lc_add, BasisAdj<real>& lB, real& la_c) {
   real s[5], P2[2], lP[2], lQc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -1067,24 +1067,27 @@ DFW_HD void normal_side_adj_comp(const Basis<real>& B, CellFn cell, real a_lo, r
     real w[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) w[c] = cell(m, c);
-    project_adj_comp<C>(B, w, lQc[m], lcs[m], lB);
+    real d[4] = {0, 0, 0, 0};
+    project_adj_comp<C>(B, w, lQc[m], d, lB);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lc_add(m, c, d[c]);
   }
 }
 
 // cell(m, c) is read once per component; callers that keep the cells in memory pass a reader that
 // reloads them, so that nothing but the accumulators lives from one component to the next.
-template <class real, class CellFn>
+template <class real, class CellFn, class AddFn>
 DFW_HD void normal_side_adj(const Basis<real>& B, CellFn cell, real a_lo, real a_c, real a_hi, real sgn_inv_dn,
-                            const Coef<real>& k, const real* lw, const real* lwn, real (*lcs)[4], BasisAdj<real>& lB,
+                            const Coef<real>& k, const real* lw, const real* lwn, AddFn lc_add, BasisAdj<real>& lB,
                             real& la_c) {
   normal_side_adj_comp<0>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<0>(B, lw),
-                          unproject_adj_q_comp<0>(B, lwn), lcs, lB, la_c);
+                          unproject_adj_q_comp<0>(B, lwn), lc_add, lB, la_c);
   normal_side_adj_comp<1>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<1>(B, lw),
-                          unproject_adj_q_comp<1>(B, lwn), lcs, lB, la_c);
+                          unproject_adj_q_comp<1>(B, lwn), lc_add, lB, la_c);
   normal_side_adj_comp<2>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<2>(B, lw),
-                          unproject_adj_q_comp<2>(B, lwn), lcs, lB, la_c);
+                          unproject_adj_q_comp<2>(B, lwn), lc_add, lB, la_c);
   normal_side_adj_comp<3>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<3>(B, lw),
-                          unproject_adj_q_comp<3>(B, lwn), lcs, lB, la_c);
+                          unproject_adj_q_comp<3>(B, lwn), lc_add, lB, la_c);
 }
 
 // Segment, one side: line(m, c) = component c of the side's line value on segment row m-2;
@@ -1123,13 +1126,13 @@ DFW_HD void segment_side(const Basis<real>& B, LineFn line, const real* al, real
   }
 }
 
-// Reverse of segment_side for the adjoints lgw, lgwt of the Gauss-point states: ll[m] (the side's
-// line values), lB and la_c accumulate.  One characteristic component at a time, as in
+// Reverse of segment_side for the adjoints lgw, lgwt of the Gauss-point states: the adjoints of the
+// side's line values go to ll_add(m, c, v); lB and la_c accumulate.  One characteristic component at a time, as in
 // normal_side_adj.
-template <int C, class real, class LineFn>
+template <int C, class real, class LineFn, class AddFn>
 DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
                                   const real (*lgw)[4], const real (*lgwt)[4], real lqv0, real lqv1, real lqd0,
-                                  real lqd1, real (*ll)[4], BasisAdj<real>& lB, real& la_c) {
+                                  real lqd1, AddFn ll_add, BasisAdj<real>& lB, real& la_c) {
   real s[5], Pc[5], lP[5] = {0, 0, 0, 0, 0}, lQc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -1153,18 +1156,21 @@ DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real*
     real w[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) w[c] = line(m, c);
-    project_adj_comp<C>(B, w, lQc[m], ll[m], lB);
+    real d[4] = {0, 0, 0, 0};
+    project_adj_comp<C>(B, w, lQc[m], d, lB);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ll_add(m, c, d[c]);
   }
 }
 
-template <class real, class LineFn>
+template <class real, class LineFn, class AddFn>
 DFW_HD void segment_side_adj(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
-                             const real (*lgw)[4], const real (*lgwt)[4], real (*ll)[4], BasisAdj<real>& lB,
+                             const real (*lgw)[4], const real (*lgwt)[4], AddFn ll_add, BasisAdj<real>& lB,
                              real& la_c) {
 #define DFW_SEG_COMP(C)                                                                                          \
   segment_side_adj_comp<C>(B, line, al, inv_dt, k, lgw, lgwt, unproject_adj_q_comp<C>(B, lgw[0]),              \
                            unproject_adj_q_comp<C>(B, lgw[1]), unproject_adj_q_comp<C>(B, lgwt[0]),            \
-                           unproject_adj_q_comp<C>(B, lgwt[1]), ll, lB, la_c)
+                           unproject_adj_q_comp<C>(B, lgwt[1]), ll_add, lB, la_c)
   DFW_SEG_COMP(0);
   DFW_SEG_COMP(1);
   DFW_SEG_COMP(2);

@@ -53,8 +53,8 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   using T = AdjTile<TF, TR>;
   __shared__ real sW[4][T::NQ][T::WN];
   __shared__ real sA[T::NQ][T::AN];
-  __shared__ real sL[8][TF * T::NQ];
-  __shared__ real sX[4][T::NT];
+  __shared__ real sL[4][2 * TF * T::NQ];  // line values, the two sides of a segment side by side
+  __shared__ real sX[4][T::NT];            // exchange of line adjoints between rows
 
   int b = blockIdx.x;
   const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
     stencil(q, cs);
     normal_side<real>(B, cs, a_of(q, 0), a_of(q, 1), a_of(q, 2), sgn_dn, k, w, dn);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) sL[4 * side + c][lidx(q, fl)] = w[c];
+    for (int c = 0; c < 4; ++c) sL[c][2 * lidx(q, fl) + side] = w[c];
   };
   if (row_needed(rr + 2)) ns_row(rr + 2, wn);
   if (rr < 4) {
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   real al[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) al[q] = sA[rr + 1 + q][fl + 1 + side];
-  auto line = [&](int m, int c) -> real { return sL[4 * side + c][lidx(rr + m, fl)]; };
+  auto line = [&](int m, int c) -> real { return sL[c][2 * lidx(rr + m, fl) + side]; };
   real gw[2][4], gwt[2][4];
 #pragma unroll
   for (int g = 0; g < 2; ++g)
@@ -295,7 +295,10 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
 #pragma unroll
     for (int c = 0; c < 4; ++c) ll[m][c] = real(0);
   real la_seg = real(0);
-  if (seg) segment_side_adj(B, line, al, inv_dt, k, lgw, lgwt, ll, lB, la_seg);
+  if (seg) {
+    auto ll_add = [&](int m, int c, real v) { ll[m][c] += v; };
+    segment_side_adj(B, line, al, inv_dt, k, lgw, lgwt, ll_add, lB, la_seg);
+  }
   real acc[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -323,7 +326,8 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   real la_ns = real(0);
   if (own) {
     auto cell = [&](int m, int c) -> real { return sW[c][rr + 2][fl + (side ? 5 - m : m)]; };
-    normal_side_adj<real>(B, cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc, lwn, lcs, lB,
+    auto lc_add = [&](int m, int c, real v) { lcs[m][c] += v; };
+    normal_side_adj<real>(B, cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc, lwn, lc_add, lB,
                           la_ns);
   }
   // basis adjoint of the pair (side 0 first on both lanes), then the two cells it is built from

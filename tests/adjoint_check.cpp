@@ -203,8 +203,10 @@ int main() {
         real la1 = 0, la2 = 0;
         auto c0 = [&](int m, int c) -> real { return cs0[m][c]; };
         auto c1 = [&](int m, int c) -> real { return cs1[m][c]; };
-        normal_side_adj<real>(B, c0, xx[24], xx[25], xx[26], idn, k, l, l + 8, lcs0, lB, la1);
-        normal_side_adj<real>(B, c1, xx[27], xx[26], xx[25], -idn, k, l + 4, l + 12, lcs1, lB, la2);
+        auto add0 = [&](int m, int c, real v) { lcs0[m][c] += v; };
+        auto add1 = [&](int m, int c, real v) { lcs1[m][c] += v; };
+        normal_side_adj<real>(B, c0, xx[24], xx[25], xx[26], idn, k, l, l + 8, add0, lB, la1);
+        normal_side_adj<real>(B, c1, xx[27], xx[26], xx[25], -idn, k, l + 4, l + 12, add1, lB, la2);
         for (int m = 0; m < 5; ++m)
           for (int c = 0; c < 4; ++c) {
             lx[4 * m + c] += lcs0[m][c];
@@ -288,7 +290,8 @@ int main() {
           for (int s = 0; s < 2; ++s) {
             auto line = [&](int m, int c) -> real { return xx[8 + 20 * s + 4 * m + c]; };
             real ll[5][4] = {};
-            segment_side_adj(B, line, al[s], idt, k, lgw[s], lgwt[s], ll, lB, lac[s]);
+            auto add = [&](int m, int c, real v) { ll[m][c] += v; };
+            segment_side_adj(B, line, al[s], idt, k, lgw[s], lgwt[s], add, lB, lac[s]);
             for (int m = 0; m < 5; ++m)
               for (int c = 0; c < 4; ++c) lx[8 + 20 * s + 4 * m + c] += ll[m][c];
           }
