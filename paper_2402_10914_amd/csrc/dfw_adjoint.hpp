@@ -263,10 +263,10 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
     real b3 = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 + real(1421461.0 / 2275.0) * u4 * u4;
     real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
     real be[4] = {b0 + k.eps, b1 + k.eps, b2 + k.eps, b3 + k.eps};
-    real ib[4], r[4], w[4];
+    const real i01 = real(1) / (be[0] * be[1]), i23 = real(1) / (be[2] * be[3]);
+    real ib[4] = {be[1] * i01, be[0] * i01, be[3] * i23, be[2] * i23}, r[4], w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      ib[q] = real(1) / be[q];
       r[q] = tau * ib[q];
       w[q] = k.d[q] * (real(1) + r[q] * r[q]);
     }
@@ -706,12 +706,13 @@ DFW_HD void maxwell_moments_adj(const Mom<real>& M, int side, const Coef<real>& 
 template <class real>
 DFW_HD void micro_slope_adj(const real* g, real U, real V, real lam, const Coef<real>& k, const real* ls_in, real* lg,
                             real& lU, real& lV, real& llam) {
-  const real K2 = k.K + real(2);
-  real B = U * U + V * V + K2 * real(0.5) / lam;
+  const real K2 = k.K2;
+  const real ilam = real(1) / lam;
+  real B = U * U + V * V + K2 * real(0.5) * ilam;
   real R4 = real(2) * g[3] - B * g[0];
   real R3 = g[2] - V * g[0];
   real R2 = g[1] - U * g[0];
-  real kap = real(4) * lam * lam / K2;
+  real kap = k.k4K2 * (lam * lam);
   real Z = R4 - real(2) * U * R2 - real(2) * V * R3;
   real s3 = kap * Z;
   real s2 = real(2) * lam * R3 - V * s3;
@@ -731,7 +732,7 @@ DFW_HD void micro_slope_adj(const real* g, real U, real V, real lam, const Coef<
   lV -= s3 * ls2;
   ls3 -= U * ls1 + V * ls2;
   // s3 = kap Z
-  llam += ls3 * Z * real(8) * lam / K2;
+  llam += ls3 * Z * real(2) * lam * k.k4K2;
   real lZ = ls3 * kap;
   real lR4 = lZ;
   lU -= real(2) * R2 * lZ;
@@ -749,7 +750,7 @@ DFW_HD void micro_slope_adj(const real* g, real U, real V, real lam, const Coef<
   lg[0] -= B * lR4;
   lU += real(2) * U * lB;
   lV += real(2) * V * lB;
-  llam += -K2 * real(0.5) / (lam * lam) * lB;
+  llam += -K2 * real(0.5) * (ilam * ilam) * lB;
 }
 
 // Adjoint of gks_flux (lF may be null when the flux itself was not requested).
@@ -772,10 +773,10 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
     real g[4], a[4], b[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) g[c] = wn[c] * q.ir;
-    micro_slope(g, q.u, q.v, lam, k, a);
+    micro_slope(g, q.u, q.v, lam, real(0.5) / lam, k, a);
 #pragma unroll
     for (int c = 0; c < 4; ++c) g[c] = wt[c] * q.ir;
-    micro_slope(g, q.u, q.v, lam, k, b);
+    micro_slope(g, q.u, q.v, lam, real(0.5) / lam, k, b);
     real t0[4], t1[4], t2[4];
     mom_psi(M, 0, 0, t0);
     mom_s_psi(M, a, 0, 0, t1);
@@ -807,14 +808,14 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
     gn[c] = Wcn[c] * irc;
     gt[c] = Wct[c] * irc;
   }
-  micro_slope(gn, Uc, Vc, lamc, k, ac);
-  micro_slope(gt, Uc, Vc, lamc, k, bc);
+  micro_slope(gn, Uc, Vc, lamc, real(0.5) / lamc, k, ac);
+  micro_slope(gt, Uc, Vc, lamc, real(0.5) / lamc, k, bc);
   real y1[4], y2[4];
   mom_s_psi(Mc, ac, 1, 0, y1);
   mom_s_psi(Mc, bc, 0, 1, y2);
 #pragma unroll
   for (int c = 0; c < 4; ++c) gA[c] = -(y1[c] + y2[c]);
-  micro_slope(gA, Uc, Vc, lamc, k, Ac);
+  micro_slope(gA, Uc, Vc, lamc, real(0.5) / lamc, k, Ac);
   real fc[4], x1[4], x2[4], xA[4];
   mom_psi(Mc, 1, 0, fc);
   mom_s_psi(Mc, ac, 2, 0, x1);
@@ -940,8 +941,8 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
       g1[c] = wn[c] * q.ir;
       g2[c] = wt[c] * q.ir;
     }
-    micro_slope(g1, q.u, q.v, lam, k, a);
-    micro_slope(g2, q.u, q.v, lam, k, b);
+    micro_slope(g1, q.u, q.v, lam, real(0.5) / lam, k, a);
+    micro_slope(g2, q.u, q.v, lam, real(0.5) / lam, k, b);
     MomAdj<real> lM;
     lM.zero();
     real la[4] = {0, 0, 0, 0}, lb[4] = {0, 0, 0, 0};

@@ -20,6 +20,7 @@ struct Coef {
   real d[4];      // WENO-AO linear weights d0..d3 (Section 3.1)
   real dr[3];     // d_k / d_3
   real inv_d3;
+  real K2, k4K2;  // K + 2 and 4 / (K + 2)
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -134,7 +135,10 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
             real(1421461.0 / 2275.0) * u4 * u4;
   // WENO-Z weights, eq. (37)
   real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
-  real r0 = tau / (b0 + k.eps), r1 = tau / (b1 + k.eps), r2 = tau / (b2 + k.eps), r3 = tau / (b3 + k.eps);
+  // 1/(b_q + eps) from two divisions: 1/(B0 B1) and 1/(B2 B3)
+  const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
+  const real i01 = real(1) / (B0 * B1), i23 = real(1) / (B2 * B3);
+  real r0 = tau * (B1 * i01), r1 = tau * (B0 * i01), r2 = tau * (B3 * i23), r3 = tau * (B2 * i23);
   real w0 = k.d[0] * (real(1) + r0 * r0);
   real w1 = k.d[1] * (real(1) + r1 * r1);
   real w2 = k.d[2] * (real(1) + r2 * r2);
@@ -252,7 +256,7 @@ struct Mom {
   real mu[7];  // u-moments 0..6 (full space, or one half space)
   real mv[6];  // v-moments 0..5 (full space)
   real mx[3];  // <xi^0>, <xi^2>, <xi^4>
-  real U, V, lam;
+  real U, V, lam, h;  // h = 1 / (2 lam)
 };
 
 template <class real>
@@ -268,6 +272,7 @@ DFW_HD void maxwell_moments(real U, real V, real lam, int side, const Coef<real>
   M.V = V;
   M.lam = lam;
   real h = real(0.5) / lam;
+  M.h = h;
   if (side == 0) {
     M.mu[0] = real(1);
     M.mu[1] = U;
@@ -322,14 +327,15 @@ DFW_HD void mom_psi(const Mom<real>& M, int a, int b, real* out) {
   out[3] = real(0.5) * (mom(M, a + 2, b, 0) + mom(M, a, b + 2, 0) + mom(M, a, b, 1));
 }
 
-// Micro-slope s with <(s . psi) psi> = g (g = dW / rho), closed-form inverse of the moment matrix.
+// Micro-slope s with <(s . psi) psi> = g (g = dW / rho), closed-form inverse of the moment matrix;
+// h = 1 / (2 lam).
 template <class real>
-DFW_HD void micro_slope(const real* g, real U, real V, real lam, const Coef<real>& k, real* s) {
-  real B = U * U + V * V + (k.K + real(2)) * real(0.5) / lam;
+DFW_HD void micro_slope(const real* g, real U, real V, real lam, real h, const Coef<real>& k, real* s) {
+  real B = U * U + V * V + k.K2 * h;
   real R4 = real(2) * g[3] - B * g[0];
   real R3 = g[2] - V * g[0];
   real R2 = g[1] - U * g[0];
-  s[3] = real(4) * lam * lam / (k.K + real(2)) * (R4 - real(2) * U * R2 - real(2) * V * R3);
+  s[3] = k.k4K2 * (lam * lam) * (R4 - real(2) * U * R2 - real(2) * V * R3);
   s[2] = real(2) * lam * R3 - V * s[3];
   s[1] = real(2) * lam * R2 - U * s[3];
   s[0] = g[0] - U * s[1] - V * s[2] - real(0.5) * s[3] * B;
@@ -361,10 +367,10 @@ DFW_HD void gks_flux(const real* wl, const real* wln, const real* wlt, const rea
     real g[4], a[4], b[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) g[c] = wn[c] * q.ir;
-    micro_slope(g, q.u, q.v, lam, k, a);
+    micro_slope(g, q.u, q.v, lam, M.h, k, a);
 #pragma unroll
     for (int c = 0; c < 4; ++c) g[c] = wt[c] * q.ir;
-    micro_slope(g, q.u, q.v, lam, k, b);
+    micro_slope(g, q.u, q.v, lam, M.h, k, b);
     real t0[4], t1[4], t2[4];
     mom_psi(M, 0, 0, t0);
     mom_s_psi(M, a, 0, 0, t1);
@@ -394,17 +400,17 @@ DFW_HD void gks_flux(const real* wl, const real* wln, const real* wlt, const rea
   real g[4], ac[4], bc[4], Ac[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) g[c] = Wcn[c] * irc;
-  micro_slope(g, Uc, Vc, lamc, k, ac);
+  micro_slope(g, Uc, Vc, lamc, M.h, k, ac);
 #pragma unroll
   for (int c = 0; c < 4; ++c) g[c] = Wct[c] * irc;
-  micro_slope(g, Uc, Vc, lamc, k, bc);
+  micro_slope(g, Uc, Vc, lamc, M.h, k, bc);
   // compatibility: <(A . psi) psi> = -<((a . psi) u + (b . psi) v) psi>
   real t1[4], t2[4];
   mom_s_psi(M, ac, 1, 0, t1);
   mom_s_psi(M, bc, 0, 1, t2);
 #pragma unroll
   for (int c = 0; c < 4; ++c) g[c] = -(t1[c] + t2[c]);
-  micro_slope(g, Uc, Vc, lamc, k, Ac);
+  micro_slope(g, Uc, Vc, lamc, M.h, k, Ac);
   real Fc[4], Mac[4], MAc[4];
   mom_psi(M, 1, 0, Fc);
   mom_s_psi(M, ac, 2, 0, t1);

@@ -75,6 +75,8 @@ __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
   for (int i = 0; i < 4; ++i) k.d[i] = real(S.d[i]);
   for (int i = 0; i < 3; ++i) k.dr[i] = real(S.d[i] / S.d[3]);
   k.inv_d3 = real(1.0 / S.d[3]);
+  k.K2 = real(S.K + 2.0);
+  k.k4K2 = real(4.0 / (S.K + 2.0));
   return k;
 }
 

@@ -27,6 +27,8 @@ static Coef<real> coef(double alpha_thres = 0.5, double c1 = 0.01, double c2 = 5
   for (int i = 0; i < 4; ++i) k.d[i] = d[i];
   for (int i = 0; i < 3; ++i) k.dr[i] = d[i] / d[3];
   k.inv_d3 = 1 / d[3];
+  k.K2 = k.K + 2;
+  k.k4K2 = 4 / (k.K + 2);
   return k;
 }
 
