@@ -15,7 +15,8 @@ launch stream) and the CPU oracle timed on a bounded sample on this host.
 Also reported: the batched form against the per-grid loop ("batched") and the cost of the
 gradient of a 100-step rollout against the rollout itself ("adjoint").
 
-Other modes:  --mode copy   plain device copy of known size (calibrates rocprofv3 FETCH/WRITE_SIZE).
+Other modes:  --mode copy      plain device copy of known size (calibrates rocprofv3 FETCH/WRITE_SIZE).
+              --mode adjoint   the gradient measurement alone.
 """
 import argparse
 import hashlib
@@ -200,7 +201,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--mode", default="step", choices=["step", "copy"])
+    ap.add_argument("--mode", default="step", choices=["step", "copy", "adjoint"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -210,6 +211,9 @@ def main():
         sys.exit(2)
     if args.mode == "copy":
         return copy_mode(args)
+    if args.mode == "adjoint":
+        print(json.dumps({"mode": "adjoint", **adjoint_compare()}))
+        return
 
     import torch
     from paper_2402_10914_amd import api, flops
