@@ -54,7 +54,7 @@ typedef struct {
  *   gamma        ratio of specific heats [1.4]
  *   cfl          dt = cfl / max over cells of max((|U|+c)/dx, (|V|+c)/dy)   [0.5]
  *   dt_fixed     if > 0, every step uses this dt instead of the CFL condition
- *   alpha_thres  DF threshold of the hybrid switch, eq. (34), strict "<" [0.5]
+ *   alpha_thres  DF threshold of the hybrid switch, eq. (42), strict "<" [0.5]
  *   d_h, d_l     linear-weight parameters of WENO-AO (Section 3.1) [0.85, 0.85]
  *   eps_weno     epsilon of the WENO-Z weights (not given by the paper) [1e-6]
  *   c1, c2       numerical collision time tau_n = c1 dt + c2 |(pl-pr)/(pl+pr)| dt (Section 2.2) [0.01, 5]
@@ -69,7 +69,7 @@ typedef struct {
 /* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */
 size_t dfw_workspace_bytes(const dfw_grid* grid, int32_t dtype);
 
-/* Advance (W, alpha) in place by nsteps S2O4 steps (eq. (24); Algorithm 1).
+/* Advance (W, alpha) in place by nsteps S2O4 steps (eq. (21); Algorithm 1).
  *   W, alpha        device, in/out.
  *   dt_hist_dev     device, optional (may be NULL): receives the nsteps time increments (FP64).
  *   t_out           host, optional: sum of the time increments actually taken.
@@ -86,7 +86,7 @@ dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params*
 dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* params, int32_t dtype,
                          void* ws, size_t ws_bytes, double* smax, int32_t* nonphys, void* stream);
 
-/* The spatial operator of one stage, eq. (2) with its time derivative (Section 2.2): for the
+/* The spatial operator of one stage, eqs. (3)-(4) with its time derivative (Section 2.2): for the
  * state W and DF field alpha, writes L(W) and dL/dt(W) ([4][ny][nx], device) and, if alpha_new
  * is non-NULL, the DF product of every cell built from this stage's Gauss-point states
  * ([ny][nx], device).  dt is used only by the gas-kinetic flux.  Stream-ordered, no sync. */
@@ -126,14 +126,14 @@ dfw_status dfw_batch_run(dfw_batch* b, void* W_flat, void* alpha_flat, int32_t n
 void dfw_batch_free(dfw_batch* b);
 
 /* ---- Reverse mode (adjoint) -------------------------------------------------------------------
- * The gradient of a scalar loss J(W^N, alpha^N) of an N-step rollout (eq. (24) steps, Section 3)
+ * The gradient of a scalar loss J(W^N, alpha^N) of an N-step rollout (eq. (21) steps, Section 3)
  * with respect to its initial state (W^0, alpha^0), by the hand-written adjoint of every operation
  * of the step: characteristic projection, WENO-AO(5,3) with WENO-Z weights and the DF hybrid
- * (Section 3.1, eqs. (11)-(21) and (34)), the DF factor (Section 3.2), the LF and GKS fluxes and
+ * (Section 3.1, eqs. (33)-(39); Section 3.3, eqs. (42)-(43)), the DF factor (Section 3.2, eqs. (40)-(41)), the LF and GKS fluxes and
  * their time derivatives (Section 2), and the two S2O4 stages.  The time steps are held fixed at a
  * recorded dt history (the CFL reduction is not differentiated).  Kinks follow one fixed
  * subgradient convention: d|x|/dx = sign(x) with sign(0) = 0; max(a, b) follows a when a >= b; the
- * switch of eq. (34) contributes no derivative (the branch taken is differentiated).
+ * switch of eq. (42) contributes no derivative (the branch taken is differentiated).
  *
  * Memory: dfw_run_ckpt stores (W, alpha) at every ckpt_every-th step; dfw_adjoint recomputes one
  * segment of ckpt_every steps at a time from its checkpoint and reverses it.  The adjoint is FP64

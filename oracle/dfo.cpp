@@ -240,7 +240,7 @@ static T smoothness(const T* c, int deg) {
   return beta;
 }
 
-/* WENO-AO(5,3) with WENO-Z weights (Section 3.1, eqs. (37)-(38)): returns the coefficients of
+/* WENO-AO(5,3) with WENO-Z weights (Section 3.1, eqs. (33)-(39)): returns the coefficients of
  * P(xi) on the target cell for the five averages Q[0..4] = Q_{i-2..i+2}. */
 template <class T>
 static void weno_ao_poly(const T* Q, const Params& prm, T* P) {
@@ -280,7 +280,7 @@ static void weno_ao_poly(const T* Q, const Params& prm, T* P) {
 }
 
 /* Section 3.3: the hybrid reconstruction of one cell.  a3 = (alpha_{i-1}, alpha_i, alpha_{i+1}).
- * If max(a3) < alpha_thres (strict, eq. (34)) the DF-weighted zero-mean quadratic
+ * If max(a3) < alpha_thres (strict, eq. (42)) the DF-weighted zero-mean quadratic
  *   Q_i + alpha_i [ (Q_{i+1}-Q_i)/dx (x - x0) + (Q_{i-1}/2 - Q_i + Q_{i+1}/2)/dx^2 (x^2 - x1) ],
  * x0 = -dx/2, x1 = dx^2/3, replaces WENO-AO; otherwise WENO-AO.  Coefficients in xi. */
 template <class T>
@@ -603,10 +603,10 @@ static void gks_flux(const T* Wl, const T* Wlx, const T* Wly, const T* Wr, const
   /* Section 2.2: numerical collision time. */
   T pl = pressure(Wl, gamma), pr = pressure(Wr, gamma);
   T tau = C1 * dt + C2 * mabs((pl - pr) / (pl + pr)) * dt;
-  /* eq. (25): time integral of the flux over [0, delta]:
+  /* eq. (22): time integral of the flux over [0, delta]:
    *   int (1 - E) dt = delta - tau (1 - e),  int t E dt = tau^2 (1 - e) - tau delta e,
    *   int t dt = delta^2 / 2,                int E dt = tau (1 - e),   e = exp(-delta / tau).
-   * The fit of eq. (26) below subtracts F(dt) - 2 F(dt/2), which cancels all but an O(dt^2)
+   * The fit of eq. (24) below subtracts F(dt) - 2 F(dt/2), which cancels all but an O(dt^2)
    * part; for plain doubles the integrals and the fit are therefore evaluated in extended
    * precision (long double) so that the cancellation stays far below FP64 parity tolerances. */
   using WT = typename Wide<T>::type;
@@ -631,7 +631,7 @@ static void gks_flux(const T* Wl, const T* Wlx, const T* Wly, const T* Wr, const
   WT Ffull[4], Fhalf[4];
   integral(dt, Ffull);
   integral(0.5 * dt, Fhalf);
-  /* eq. (26) fitted to F(dt) and F(dt/2): F^n dt + F_t dt^2/2 = F(dt), F^n dt/2 + F_t dt^2/8 = F(dt/2). */
+  /* eq. (23) fitted to F(dt) and F(dt/2) (the system of eq. (24)): F^n dt + F_t dt^2/2 = F(dt), F^n dt/2 + F_t dt^2/8 = F(dt/2). */
   const WT dtw = WT(dt);
   for (int k = 0; k < 4; ++k) {
     F[k] = T((WT(4.0) * Fhalf[k] - Ffull[k]) / dtw);
@@ -832,7 +832,7 @@ static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Gri
   }
 }
 
-/* eq. (2) with the Gauss quadrature: L = -(1/|Omega|) sum_p |l_p| sum_m A_m F(x_pm) . n_p. */
+/* eqs. (3)-(4), the Gauss quadrature: L = -(1/|Omega|) sum_p |l_p| sum_m A_m F(x_pm) . n_p. */
 template <class T>
 static void spatial_operator(const T* Win, const T* alpha, const Grid& G, const Params& prm,
                              double dt, T* Lout, T* Ltout, T* alpha_new) {
@@ -892,7 +892,7 @@ static bool max_speed(const double* W, const Grid& G, double gamma, double* smax
   return ok;
 }
 
-/* Eq. (24), S2O4:  W* = W^n + dt/2 L^n + dt^2/8 L_t^n,
+/* Eq. (21), S2O4:  W* = W^n + dt/2 L^n + dt^2/8 L_t^n,
  *                  W^{n+1} = W^n + dt L^n + dt^2/6 (L_t^n + 2 L_t^*).
  * op(W, L, Lt, stage) evaluates the operator and its time derivative; only L_t of the second
  * stage enters the update. */

@@ -3,7 +3,7 @@
 // Convention: for y = f(x), f_adj(x, ..., ly, lx) adds (dy/dx)^T ly into lx (accumulates; callers
 // zero the adjoint arrays).  Each adjoint recomputes the forward intermediates it needs from the
 // primal inputs.  Kinks follow a fixed subgradient convention: d|x| = sign(x) with sign(0) = 0;
-// max(a, b) routes to a when a >= b; the hybrid switch of eq. (34) has zero derivative (the branch
+// max(a, b) routes to a when a >= b; the hybrid switch of eq. (42) has zero derivative (the branch
 // taken is differentiated); dt is held fixed.
 #pragma once
 

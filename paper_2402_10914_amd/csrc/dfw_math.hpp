@@ -133,7 +133,7 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   real e2 = u2 + real(123.0 / 455.0) * u4;
   real b3 = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 +
             real(1421461.0 / 2275.0) * u4 * u4;
-  // WENO-Z weights, eq. (37)
+  // WENO-Z weights, eqs. (36)-(37)
   real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
   // 1/(b_q + eps) from two divisions: 1/(B0 B1) and 1/(B2 B3)
   const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
@@ -342,7 +342,7 @@ DFW_HD void micro_slope(const real* g, real U, real V, real lam, real h, const C
 }
 
 // GKS flux at one Gauss point.  wl/wr: states; wln/wrn: normal derivatives; wlt/wrt: tangential
-// derivatives.  Outputs F (if WANT_F) and dF/dt by the S2O4 fit of eq. (26) to the time
+// derivatives.  Outputs F (if WANT_F) and dF/dt by the S2O4 fit of eqs. (23)-(25) to the time
 // integrals over dt and dt/2, written in closed form:
 //   F    = cf1 Fc + cf2 (Ma_c - Ma_lr) + (1 - cf1) F_lr
 //   F_t  = ct1 (Fc - F_lr) + ct2 (Ma_c - Ma_lr) + MA_c

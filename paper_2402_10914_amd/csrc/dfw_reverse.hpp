@@ -14,7 +14,7 @@
 //                 reads: 26 values, each with exactly one writer (no atomics).
 //   k_adj_gather  one thread per cell: sums the interface-buffer entries whose stencil cell maps to
 //                 it (ghost cells fold back through the boundary map) in a fixed order, and applies
-//                 the stage recurrences of eq. (24) in reverse.
+//                 the stage recurrences of eq. (21) in reverse.
 // Results are bitwise reproducible and independent of the tile shape.
 #pragma once
 

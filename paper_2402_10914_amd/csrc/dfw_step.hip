@@ -9,8 +9,8 @@
 //            the two Gauss points of each of its TR segments, the flux and its time derivative, and
 //            the DF of the Gauss points.  The thread that reconstructs a segment in the normal sweep
 //            also owns it in the tangential sweep, so the normal derivatives stay in registers.
-//   update:  one thread per cell assembles L and dL/dt from the four face sums (eq. (2)) and
-//            applies eq. (24); the second update also forms alpha^{n+1} (Section 3.2), checks
+//   update:  one thread per cell assembles L and dL/dt from the four face sums (eqs. (3)-(4)) and
+//            applies eq. (21); the second update also forms alpha^{n+1} (Section 3.2), checks
 //            positivity and reduces the signal speed for the next dt (wavefront shuffle, LDS,
 //            one 64-bit atomic max per workgroup on the bit pattern of a non-negative double).
 // Every grid has its own control block (dt, time, status), so the grids of a batch advance with

@@ -4,7 +4,7 @@ finite differences.
 * Whole gradient, element by element, on tiny grids: the oracle's forward-mode derivative (dual
   numbers through its plain FP64 step) along every unit direction gives each entry of
   dJ/d(W^0, alpha^0) for J = <gW, W^N> + <gA, alpha^N>.  Cases: smooth data, a DF field that puts
-  part of the grid on the DF branch of eq. (34), transmissive boundaries, LF and GKS.
+  part of the grid on the DF branch of eq. (42), transmissive boundaries, LF and GKS.
 * Dot-product test on larger grids: <grad J, v> against the oracle's directional derivative.
 * Central differences (eps = 1e-6) of the HIP forward on the 64x64 instance of the adjoint
   workload (density wave plus Gaussian bumps, LF, CFL 0.5, 100 steps, loss = L2 misfit of the

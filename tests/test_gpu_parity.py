@@ -73,7 +73,7 @@ def _problem(kind, nx, ny, seed=5):
 
 
 def scaled_l1(Lt_g, Lt_o, L_o, dt):
-    """dL/dt enters the state only as dt^2 L_t next to dt L (eq. (24)), so its error is measured
+    """dL/dt enters the state only as dt^2 L_t next to dt L (eq. (21)), so its error is measured
     on that scale: sum|dt (Lt_g - Lt_o)| / (sum|L_o| + sum|dt Lt_o|), per component.  (Where the
     fluxes are nearly piecewise constant dL/dt is a cancellation of much larger terms.)"""
     return max(float(dt * np.abs(Lt_g[c] - Lt_o[c]).sum() / (np.abs(L_o[c]).sum() + dt * np.abs(Lt_o[c]).sum()))

@@ -124,7 +124,7 @@ def test_hybrid_branch_special_cases():
     P = O.hybrid(Q, [0.1, 0.3, 0.2], prm)
     mean = sum(P[n] * ((0.0) - (-1.0) ** (n + 1)) / (n + 1) for n in range(5))
     assert mean == pytest.approx(Q[2], abs=1e-14)
-    # max(alpha) == threshold keeps WENO-AO (strict inequality of eq. (34))
+    # max(alpha) == threshold keeps WENO-AO (strict inequality of eq. (42))
     np.testing.assert_allclose(O.hybrid(Q, [0.5, 0.1, 0.1], prm), O.weno_ao(Q, prm), atol=0)
 
 
@@ -326,7 +326,7 @@ def test_df_special_cases():
 
 
 # ----------------------------------------------------------------------------------------------
-# Time integration (eq. (24)) and the full step
+# Time integration (eq. (21)) and the full step
 # ----------------------------------------------------------------------------------------------
 
 def test_s2o4_is_fourth_order_taylor_on_linear_ode():
@@ -542,7 +542,7 @@ def test_tangent_matches_central_differences(flux):
 def test_tangent_of_alpha_and_df_branch_matches_central_differences(flux):
     """The forward-mode derivative of both outputs (W^N and alpha^N) along a direction in both
     inputs (W^0 and alpha^0), on cell-wise random states with part of the grid on the DF branch of
-    eq. (34), against central differences of the oracle's own steps (fixed dt): the gap at
+    eq. (42), against central differences of the oracle's own steps (fixed dt): the gap at
     h = 1e-6 is below 1e-6 relative.  Pressure and velocity vary from cell to cell so that no
     kink argument (|p_l - p_r|, the LF speed max) sits at zero."""
     rng = np.random.default_rng(71)
