@@ -22,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,11 +35,24 @@ PEAK_HBM = 8000.0       # GB/s
 BYTES_PER_CELL_UPDATE = {8: 216, 4: 108}  # algorithmic HBM bytes of one S2O4 step per cell
 
 
-def kernel_source_hash():
+def _code_only(src: str) -> str:
+    """Source text without comments and whitespace (so that edits of comments keep the hash)."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return re.sub(r"\s+", "", src)
+
+
+def kernel_source_hash(read=None):
+    """Hash of the code of the forward kernels (dfw_math.hpp, dfw_step.hip)."""
     h = hashlib.sha256()
     for f in ("dfw_math.hpp", "dfw_step.hip"):
-        with open(os.path.join(ROOT, "paper_2402_10914_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        path = os.path.join(ROOT, "paper_2402_10914_amd", "csrc", f)
+        if read:
+            text = read(f)
+        else:
+            with open(path) as fh:
+                text = fh.read()
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 
