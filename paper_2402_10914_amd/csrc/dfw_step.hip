@@ -510,10 +510,10 @@ static void timed(int kind, hipStream_t st, Launch launch) {
     return;
   }
   hipEvent_t a = g_prof.take(), b = g_prof.take();
-  if (a) hipEventRecord(a, st);
+  const bool ok_a = a && hipEventRecord(a, st) == hipSuccess;
   launch();
-  if (b) hipEventRecord(b, st);
-  if (a && b) g_prof.recs.push_back({kind, a, b});
+  const bool ok_b = b && hipEventRecord(b, st) == hipSuccess;
+  if (ok_a && ok_b) g_prof.recs.push_back({kind, a, b});  // a launch without both events is not timed
 }
 
 // Interface tile shapes (TF interfaces x TR segments); index 0 is the library default.
