@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
                 ("alpha_thres", ctypes.c_double), ("d_h", ctypes.c_double), ("d_l", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
-                ("flux", ctypes.c_int32)]
+                ("flux", ctypes.c_int32), ("time_limiter", ctypes.c_int32)]
 
 
 _lib = None
@@ -59,6 +59,7 @@ def lib():
         L.dfo_max_speed.restype = ctypes.c_int
         L.dfo_run.restype = ctypes.c_int
         L.dfo_smoothness.restype = ctypes.c_double
+        L.dfo_limiter_weight.restype = ctypes.c_double
         L.dfo_df_gp.restype = ctypes.c_double
         L.dfo_moment.restype = ctypes.c_double
         L.dfo_moment.argtypes = [dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -86,9 +87,9 @@ def make_grid(nx, ny, dx, dy, bc_x=BC_PERIODIC, bc_y=None) -> Grid:
 
 
 def make_params(flux=FLUX_LF, gamma=1.4, cfl=0.5, dt_fixed=0.0, alpha_thres=0.5, d_h=0.85, d_l=0.85,
-                eps_weno=1e-6, c1=0.01, c2=5.0) -> Params:
+                eps_weno=1e-6, c1=0.01, c2=5.0, time_limiter=0) -> Params:
     return Params(float(gamma), float(cfl), float(dt_fixed), float(alpha_thres), float(d_h), float(d_l),
-                  float(eps_weno), float(c1), float(c2), int(flux))
+                  float(eps_weno), float(c1), float(c2), int(flux), int(time_limiter))
 
 
 def max_speed(W: np.ndarray, grid: Grid, params: Params):
@@ -152,6 +153,12 @@ def weno_ao(Q, params: Params) -> np.ndarray:
     P = np.zeros(5)
     lib().dfo_weno_ao(_p(Q), ctypes.byref(params), _p(P))
     return P
+
+
+def limiter_weight(Q, params: Params) -> float:
+    """Non-linear time-limiter weight of eq. (29) for one five-average stencil."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    return lib().dfo_limiter_weight(_p(Q), ctypes.byref(params))
 
 
 def hybrid(Q, a3, params: Params) -> np.ndarray:

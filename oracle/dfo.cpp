@@ -93,6 +93,7 @@ template <class T> T mabs(const T& a) {
 }
 /* max(a, b) routes to a when a >= b. */
 template <class T> T mmax(const T& a, const T& b) { return val(a) >= val(b) ? a : b; }
+template <class T> T mmin(const T& a, const T& b) { return val(a) <= val(b) ? a : b; }
 template <class T> T sq(const T& a) { return a * a; }
 
 /* Extended-precision companion type used where a formula of the paper cancels catastrophically. */
@@ -114,6 +115,7 @@ struct Grid {
 struct Params {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
+  int32_t time_limiter; /* 1: eqs. (27)-(29) for the second-stage update */
 };
 
 /* ------------------------------------------------------------------------------------------ */
@@ -277,6 +279,34 @@ static void weno_ao_poly(const T* Q, const Params& prm, T* P) {
     for (int k = 0; k < 3; ++k) s = s + wb[k] * p[k][n];
     P[n] = s;
   }
+}
+
+/* Section 2.2, eq. (29): the non-linear time-limiter weight of one reconstruction (five averages
+ * Q[0..4] = Q_{i-2..i+2} of one characteristic component), from the smoothness indicators of
+ * eq. (38) and the global indicator of eq. (37) of the WENO-AO stencils of the cell:
+ *   a1 = 1 + (tau_Z / (beta_min + eps))^2,  a2 = 1 + (tau_Z / (beta_max + eps))^2,
+ *   alpha = 2 a2 / (a1 + a2),
+ * beta_min, beta_max over the four indicators beta_0..beta_3 (reading R28). */
+template <class T>
+static T limiter_weight(const T* Q, const Params& prm) {
+  const Candidates& C = candidates();
+  T beta[4];
+  for (int k = 0; k < 4; ++k) {
+    T p[5];
+    for (int n = 0; n < 5; ++n) {
+      T s = T(0.0);
+      for (int m = 0; m < 5; ++m)
+        if (C.coef[k][n][m] != 0.0) s = s + C.coef[k][n][m] * Q[m];
+      p[n] = s;
+    }
+    beta[k] = smoothness(p, C.deg[k]);
+  }
+  T tau = (mabs(beta[3] - beta[0]) + mabs(beta[3] - beta[1]) + mabs(beta[3] - beta[2])) / 3.0;
+  T bmin = mmin(mmin(beta[0], beta[1]), mmin(beta[2], beta[3]));
+  T bmax = mmax(mmax(beta[0], beta[1]), mmax(beta[2], beta[3]));
+  T a1 = 1.0 + sq(tau / (bmin + prm.eps_weno));
+  T a2 = 1.0 + sq(tau / (bmax + prm.eps_weno));
+  return 2.0 * a2 / (a1 + a2);
 }
 
 /* Section 3.3: the hybrid reconstruction of one cell.  a3 = (alpha_{i-1}, alpha_i, alpha_{i+1}).
@@ -696,8 +726,9 @@ static Ghosted<T> fill_ghosts(const T* A, int comps, const Grid& G, int g) {
 /* dir = 0: x-interfaces (normal x, tangential y); dir = 1: y-interfaces.                     */
 /* ------------------------------------------------------------------------------------------ */
 template <class T>
-struct FaceData { /* per interface: face-averaged flux, its time derivative, DF of the 2 GPs */
-  std::vector<T> F, Ft, a1, a2;
+struct FaceData { /* per interface: face-averaged flux, its time derivative, DF of the 2 GPs, and
+                   the time-limiter weight omega of eq. (29) */
+  std::vector<T> F, Ft, a1, a2, om;
 };
 
 template <class T>
@@ -718,6 +749,9 @@ static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Gri
   /* normal sweep: line values (left/right) and their normal derivatives, rows -2..Nt+1 */
   std::vector<T> lineL((size_t)TR * NF * 4), lineR((size_t)TR * NF * 4), lineLn((size_t)TR * NF * 4),
       lineRn((size_t)TR * NF * 4);
+  /* eq. (29): omega of interface f on row t = min over the characteristic components of the
+   * weights of the two reconstructions beside it (reading R28) */
+  std::vector<T> omega(prm.time_limiter ? (size_t)TR * NF : 0);
 #pragma omp parallel for schedule(static)
   for (int rt = 0; rt < TR; ++rt) {
     int t = rt + TR0;
@@ -747,6 +781,18 @@ static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Gri
         qr[c] = poly_eval(P, 4, -1.0);                /* left edge of cell f */
         qrn[c] = poly_deriv_eval(P, 4, -1.0) / dn;
       }
+      if (prm.time_limiter) {
+        T om = T(1.0);
+        for (int c = 0; c < 4; ++c) {
+          T sl[5], sr[5];
+          for (int m = 0; m < 5; ++m) {
+            sl[m] = Q[m][c];
+            sr[m] = Q[m + 1][c];
+          }
+          om = mmin(om, mmin(limiter_weight(sl, prm), limiter_weight(sr, prm)));
+        }
+        omega[(size_t)rt * NF + f] = om;
+      }
       size_t o = ((size_t)rt * NF + f) * 4;
       matvec4(R, ql, &lineL[o]);
       matvec4(R, qln, &lineLn[o]);
@@ -759,6 +805,10 @@ static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Gri
   out.Ft.assign((size_t)Nt * NF * 4, T(0.0));
   out.a1.assign((size_t)Nt * NF, T(0.0));
   out.a2.assign((size_t)Nt * NF, T(0.0));
+  out.om.assign(prm.time_limiter ? (size_t)Nt * NF : 0, T(1.0));
+  if (prm.time_limiter)
+    for (int t = 0; t < Nt; ++t)
+      for (int f = 0; f < NF; ++f) out.om[(size_t)t * NF + f] = omega[(size_t)(t - TR0) * NF + f];
   const double xi_gp[2] = {-0.5 - std::sqrt(3.0) / 6.0, -0.5 + std::sqrt(3.0) / 6.0};
 #pragma omp parallel for schedule(static)
   for (int t = 0; t < Nt; ++t) {
@@ -835,7 +885,7 @@ static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Gri
 /* eqs. (3)-(4), the Gauss quadrature: L = -(1/|Omega|) sum_p |l_p| sum_m A_m F(x_pm) . n_p. */
 template <class T>
 static void spatial_operator(const T* Win, const T* alpha, const Grid& G, const Params& prm,
-                             double dt, T* Lout, T* Ltout, T* alpha_new) {
+                             double dt, T* Lout, T* Ltout, T* alpha_new, T* Ltlim = nullptr) {
   Ghosted<T> Wg = fill_ghosts(Win, 4, G, GW);
   Ghosted<T> Ag = fill_ghosts(alpha, 1, G, GA);
   FaceData<T> X, Y;
@@ -856,6 +906,11 @@ static void spatial_operator(const T* Win, const T* alpha, const Grid& G, const 
         size_t o = ((size_t)c * ny + j) * nx + i;
         Lout[o] = -(s / area);
         Ltout[o] = -(st / area);
+        if (Ltlim) { /* eq. (28): each face's time derivative weighted by its omega */
+          T sl = G.dy * (X.om[east] * X.Ft[east * 4 + c]) - G.dy * (X.om[west] * X.Ft[west * 4 + c]) +
+                 G.dx * (Y.om[north] * Y.Ft[north * 4 + c]) - G.dx * (Y.om[south] * Y.Ft[south * 4 + c]);
+          Ltlim[o] = -(sl / area);
+        }
       }
       if (alpha_new) { /* Section 3.2: product over the 4 interfaces and their 2 Gauss points */
         T a = X.a1[west] * X.a2[west];
@@ -905,8 +960,24 @@ static void s2o4(T* W, size_t n, double dt, Op op) {
   for (size_t k = 0; k < n; ++k) W[k] = W[k] + dt * L0[k] + (dt * dt / 6.0) * (Lt0[k] + 2.0 * Lt1[k]);
 }
 
+/* Section 2.2, eq. (27): S2O4 with the non-linear time limiter.  W* as in eq. (21) (reading R28);
+ *   W^{n+1} = W^n + dt L^n + dt^2/2 L_t^n - dt^2/3 ~L_t^n + dt^2/3 ~L_t^*,
+ * ~L_t the limited time derivatives of eq. (28). */
+template <class T>
+static void s2o4_limited_step(T* W, T* alpha, const Grid& G, const Params& prm, double dt) {
+  const size_t N = (size_t)G.nx * G.ny, n = 4 * N;
+  std::vector<T> L0(n), Lt0(n), Lt0l(n), Ws(n), L1(n), Lt1(n), Lt1l(n), an(N);
+  spatial_operator(W, alpha, G, prm, dt, L0.data(), Lt0.data(), (T*)nullptr, Lt0l.data());
+  for (size_t k = 0; k < n; ++k) Ws[k] = W[k] + 0.5 * dt * L0[k] + (dt * dt / 8.0) * Lt0[k];
+  spatial_operator(Ws.data(), alpha, G, prm, dt, L1.data(), Lt1.data(), an.data(), Lt1l.data());
+  for (size_t k = 0; k < n; ++k)
+    W[k] = W[k] + dt * L0[k] + (dt * dt / 2.0) * Lt0[k] - (dt * dt / 3.0) * Lt0l[k] + (dt * dt / 3.0) * Lt1l[k];
+  for (size_t k = 0; k < N; ++k) alpha[k] = an[k];
+}
+
 template <class T>
 static void s2o4_step(T* W, T* alpha, const Grid& G, const Params& prm, double dt) {
+  if (prm.time_limiter) return s2o4_limited_step(W, alpha, G, prm, dt);
   const size_t N = (size_t)G.nx * G.ny;
   std::vector<T> an(N);
   s2o4(W, 4 * N, dt, [&](const T* w, T* L, T* Lt, int stage) {
@@ -932,12 +1003,13 @@ struct dfo_grid {
 };
 struct dfo_params {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
-  int32_t flux;
+  int32_t flux, time_limiter;
 };
 
 static Grid to_grid(const dfo_grid* g) { return Grid{g->nx, g->ny, g->dx, g->dy, g->bc_x, g->bc_y}; }
 static Params to_params(const dfo_params* p) {
-  return Params{p->gamma, p->cfl, p->dt_fixed, p->alpha_thres, p->d_h, p->d_l, p->eps_weno, p->c1, p->c2, p->flux};
+  return Params{p->gamma, p->cfl, p->dt_fixed, p->alpha_thres, p->d_h, p->d_l, p->eps_weno, p->c1, p->c2, p->flux,
+                p->time_limiter};
 }
 
 /* 0 on success, 1 when the state holds a non-positive density/pressure or a non-finite value. */
@@ -1018,6 +1090,9 @@ void dfo_candidate(int32_t k, double* coef) {
 double dfo_smoothness(const double* coef, int32_t deg) { return smoothness(coef, deg); }
 
 void dfo_weno_ao(const double* Q, const dfo_params* p, double* P) { weno_ao_poly(Q, to_params(p), P); }
+
+/* eq. (29) weight of one five-average stencil. */
+double dfo_limiter_weight(const double* Q, const dfo_params* p) { return limiter_weight(Q, to_params(p)); }
 
 void dfo_hybrid(const double* Q, const double* a3, const dfo_params* p, double* P) {
   hybrid_poly(Q, a3, to_params(p), P);

@@ -577,3 +577,101 @@ def test_tangent_of_alpha_and_df_branch_matches_central_differences(flux):
 
     fd = (J(1e-6) - J(-1e-6)) / 2e-6
     assert abs(fd - tan) <= 1e-6 * abs(tan), (fd, tan)
+
+
+# ------------------------------------------------------------------------------------------------
+# Non-linear time limiter (Section 2.2, eqs. (27)-(29))
+# ------------------------------------------------------------------------------------------------
+
+def test_limiter_weight_closed_cases():
+    """eq. (29): constant and linear data have tau_Z = 0, hence weight exactly 1 (linear data: every
+    candidate is the same line, all four indicators are equal); a jump drives the weight to 0."""
+    p = O.make_params()
+    assert O.limiter_weight([1.3] * 5, p) == 1.0
+    lin = 0.7 + 0.25 * np.arange(5)
+    assert abs(O.limiter_weight(lin, p) - 1.0) <= 1e-12
+    assert O.limiter_weight([1.0, 1.0, 1.0, 2.0, 2.0], p) < 1e-10
+    assert O.limiter_weight([2.0, 2.0, 1.0, 1.0, 1.0], p) < 1e-10
+    # the weight lies in (0, 1]: beta_min <= beta_max
+    rng = np.random.default_rng(29)
+    for _ in range(50):
+        w = O.limiter_weight(rng.normal(size=5), p)
+        assert 0.0 < w <= 1.0
+
+
+def test_limiter_weight_converges_to_one_on_smooth_data():
+    """On samples of a smooth function with spacing h, tau_Z = O(h^5) against indicators
+    O(h^2), so 1 - weight = O(h^6): halving h divides it by at least 2^5."""
+    p = O.make_params(eps_weno=1e-40)  # keep eps out of the asymptotics
+    def one_minus(h):
+        x = 0.3 + h * np.arange(-2, 3)
+        return 1.0 - O.limiter_weight(np.sin(x) + 0.5 * x * x, p)
+    d = [one_minus(0.1 / 2 ** k) for k in range(3)]
+    assert all(d[k] > 0 for k in range(3))
+    assert d[0] / d[1] > 2 ** 5 and d[1] / d[2] > 2 ** 5, d
+
+
+def _riemann_small_tl(n=24, flux=0, seed=5):
+    pr = WL.riemann4(n, n, seed=seed)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    smax, ok = O.max_speed(pr.W, g, O.make_params())
+    assert ok
+    return pr, g, 0.4 / smax
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_limited_step_reduces_to_eq21_when_weights_are_one(flux):
+    """With eps so large that every weight rounds to exactly 1, eq. (27) is eq. (21) rearranged:
+    both steps agree to rounding (a wrong coefficient in either would differ by O(dt^2 L_t)).
+    Smooth data with cell-wise perturbations, on which the linear weights this eps implies are
+    stable."""
+    pr = WL.density_wave(20, 18)
+    rng = np.random.default_rng(27)
+    pr.W = pr.W * (1.0 + 0.02 * rng.standard_normal(pr.W.shape))
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy)
+    smax, _ = O.max_speed(pr.W, g, O.make_params())
+    dt = 0.4 / smax
+    kw = dict(flux=flux, dt_fixed=dt, eps_weno=1e30)
+    Wa, Aa, _, _, fa = O.run(pr.W, pr.alpha, g, O.make_params(**kw), 3)
+    Wb, Ab, _, _, fb = O.run(pr.W, pr.alpha, g, O.make_params(time_limiter=1, **kw), 3)
+    assert fa == -1 and fb == -1
+    assert np.abs(Wa - Wb).max() <= 1e-13 * np.abs(Wa).max()
+    assert np.abs(Aa - Ab).max() <= 1e-13  # alpha from states that differ by rounding
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_limiter_acts_on_discontinuities_and_conserves(flux):
+    """Riemann data on a periodic grid: the limited step differs from eq. (21) near the jumps, keeps
+    the sums of the conserved quantities (each face's weight is shared by its two cells) and
+    leaves smooth regions unchanged to rounding."""
+    pr, g, dt = _riemann_small_tl(flux=flux)
+    gp = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, O.BC_PERIODIC)
+    W0 = pr.W
+    Wa, _, _, _, fa = O.run(W0, pr.alpha, gp, O.make_params(flux=flux, dt_fixed=dt), 2)
+    Wb, _, _, _, fb = O.run(W0, pr.alpha, gp, O.make_params(flux=flux, dt_fixed=dt, time_limiter=1), 2)
+    assert fa == -1 and fb == -1
+    diff = np.abs(Wa - Wb).max(axis=0)
+    assert diff.max() > 1e-8 * np.abs(Wa).max()
+    s0, s1 = W0.sum(axis=(1, 2)), Wb.sum(axis=(1, 2))
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * np.abs(W0).sum(axis=(1, 2)))
+    # cells far (> 8 cells, two steps of a 6-cell stencil) from every jump of the initial state
+    jump = np.zeros(W0.shape[1:], dtype=bool)
+    for ax in (0, 1):
+        d = np.abs(np.diff(W0[0], axis=ax, append=np.take(W0[0], [0], axis=ax))) > 1e-12
+        jump |= d
+    far = ~jump
+    for ax in (0, 1):
+        for sh in range(-8, 9):
+            far &= ~np.roll(jump, sh, axis=ax)
+    if far.any():
+        assert diff[far].max() <= 1e-13 * np.abs(Wa).max()
+
+
+def test_limited_density_wave_matches_unlimited_closely():
+    """Smooth periodic data: the weights are 1 - O(h^6), so the limited run stays within 1e-10 of
+    eq. (21) over 10 steps on the 64x64 density wave."""
+    pr = WL.density_wave(64)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy)
+    Wa, _, _, _, _ = O.run(pr.W, pr.alpha, g, O.make_params(cfl=0.5), 10)
+    Wb, _, _, _, _ = O.run(pr.W, pr.alpha, g, O.make_params(cfl=0.5, time_limiter=1), 10)
+    assert np.abs(Wa - Wb).max() <= 1e-10
