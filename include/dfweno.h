@@ -59,11 +59,15 @@ typedef struct {
  *   eps_weno     epsilon of the WENO-Z weights (not given by the paper) [1e-6]
  *   c1, c2       numerical collision time tau_n = c1 dt + c2 |(pl-pr)/(pl+pr)| dt (Section 2.2) [0.01, 5]
  *   flux         DFW_FLUX_LF or DFW_FLUX_GKS
- *   tile         interface tile shape, 0 <= tile < dfw_num_tiles() [0]; results do not depend on it */
+ *   tile         interface tile shape, 0 <= tile < dfw_num_tiles() [0]; results do not depend on it
+ *   time_limiter 1: the non-linear time limiter of Section 2.2 (eqs. (27)-(29)) for the second-stage
+ *                update; 0: plain eq. (21) [0].  The limiter's epsilon is eps_weno.  dfw_rhs
+ *                returns the unlimited dL/dt; dfw_adjoint rejects time_limiter = 1. */
 typedef struct {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
   int32_t tile;
+  int32_t time_limiter;
 } dfw_params;
 
 /* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */

@@ -30,7 +30,7 @@ class dfw_params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
                 ("alpha_thres", ctypes.c_double), ("d_h", ctypes.c_double), ("d_l", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
-                ("flux", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("flux", ctypes.c_int32), ("tile", ctypes.c_int32), ("time_limiter", ctypes.c_int32)]
 
 
 class DFWError(RuntimeError):

@@ -35,11 +35,12 @@ class Params:
     c1: float = 0.01
     c2: float = 5.0
     tile: int = 0  # interface tile shape (performance only; see tile_shapes())
+    time_limiter: int = 0  # 1: non-linear time limiter of Section 2.2, eqs. (27)-(29)
 
     def struct(self) -> _lib.dfw_params:
         return _lib.dfw_params(float(self.gamma), float(self.cfl), float(self.dt_fixed), float(self.alpha_thres),
                                float(self.d_h), float(self.d_l), float(self.eps_weno), float(self.c1),
-                               float(self.c2), int(self.flux), int(self.tile))
+                               float(self.c2), int(self.flux), int(self.tile), int(self.time_limiter))
 
 
 def tile_shapes():

@@ -85,6 +85,34 @@ DFW_HD void unproject(const Basis<real>& B, const real* q, real* w) {
 //   paper's zero-mean quadratic with x0 = -dx/2, x1 = dx^2/3 written through p_1.
 // NDEG limits the coefficients produced (2 = value and slope at the edge only).
 // ------------------------------------------------------------------------------------------------
+// Smoothness indicators beta_0..beta_3 of eq. (38) of the four WENO-AO stencils of a cell (five
+// averages Q[0..4] = Q_{i-2..i+2}): Jiang-Shu forms for the three quadratics, closed form for the
+// quartic.
+// ------------------------------------------------------------------------------------------------
+template <class real>
+DFW_HD void weno_indicators(const real* Q, real* b) {
+  const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
+  const real k1312 = real(13.0 / 12.0), k14 = real(0.25);
+  real t, s;
+  t = Q0 - real(2) * Q1 + Q2;
+  s = Q0 - real(4) * Q1 + real(3) * Q2;
+  b[0] = k1312 * t * t + k14 * s * s;
+  t = Q1 - real(2) * Q2 + Q3;
+  s = Q1 - Q3;
+  b[1] = k1312 * t * t + k14 * s * s;
+  t = Q2 - real(2) * Q3 + Q4;
+  s = real(3) * Q2 - real(4) * Q3 + Q4;
+  b[2] = k1312 * t * t + k14 * s * s;
+  real u1 = (real(11) * (Q0 - Q4) + real(82) * (Q3 - Q1)) * real(1.0 / 120.0);
+  real u2 = (real(40) * (Q1 + Q3) - real(3) * (Q0 + Q4) - real(74) * Q2) * real(1.0 / 56.0);
+  real u3 = (real(2) * (Q1 - Q3) + Q4 - Q0) * real(1.0 / 12.0);
+  real u4 = (Q0 - real(4) * Q1 + real(6) * Q2 - real(4) * Q3 + Q4) * real(1.0 / 24.0);
+  real e1 = u1 + real(0.1) * u3;
+  real e2 = u2 + real(123.0 / 455.0) * u4;
+  b[3] = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 + real(1421461.0 / 2275.0) * u4 * u4;
+}
+
+// ------------------------------------------------------------------------------------------------
 template <class real, int NDEG>
 DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, real* P) {
   const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
@@ -113,26 +141,9 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   real c2 = (-Q0 + real(6) * Q1 - real(8) * Q2 + real(2) * Q3 + Q4) * real(0.125);
   real c3 = (-Q1 + real(3) * Q2 - real(3) * Q3 + Q4) * real(1.0 / 6.0);
   real c4 = (Q0 - real(4) * Q1 + real(6) * Q2 - real(4) * Q3 + Q4) * real(1.0 / 24.0);
-  // smoothness indicators: Jiang-Shu forms for the quadratics, closed form for the quartic
-  const real k1312 = real(13.0 / 12.0), k14 = real(0.25);
-  real t;
-  t = Q0 - real(2) * Q1 + Q2;
-  real s = Q0 - real(4) * Q1 + real(3) * Q2;
-  real b0 = k1312 * t * t + k14 * s * s;
-  t = Q1 - real(2) * Q2 + Q3;
-  s = Q1 - Q3;
-  real b1 = k1312 * t * t + k14 * s * s;
-  t = Q2 - real(2) * Q3 + Q4;
-  s = real(3) * Q2 - real(4) * Q3 + Q4;
-  real b2 = k1312 * t * t + k14 * s * s;
-  real u1 = (real(11) * (Q0 - Q4) + real(82) * (Q3 - Q1)) * real(1.0 / 120.0);
-  real u2 = (real(40) * (Q1 + Q3) - real(3) * (Q0 + Q4) - real(74) * Q2) * real(1.0 / 56.0);
-  real u3 = (real(2) * (Q1 - Q3) + Q4 - Q0) * real(1.0 / 12.0);
-  real u4 = c4;
-  real e1 = u1 + real(0.1) * u3;
-  real e2 = u2 + real(123.0 / 455.0) * u4;
-  real b3 = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 +
-            real(1421461.0 / 2275.0) * u4 * u4;
+  real bq[4];
+  weno_indicators(Q, bq);
+  const real b0 = bq[0], b1 = bq[1], b2 = bq[2], b3 = bq[3];
   // WENO-Z weights, eqs. (36)-(37)
   real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
   // 1/(b_q + eps) from two divisions: 1/(B0 B1) and 1/(B2 B3)
@@ -164,6 +175,51 @@ template <class real>
 DFW_HD void eval_poly_at(const real* P, real xi, real& val, real& der) {
   val = (((P[4] * xi + P[3]) * xi + P[2]) * xi + P[1]) * xi + P[0];
   der = ((real(4) * P[4] * xi + real(3) * P[3]) * xi + real(2) * P[2]) * xi + P[1];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Non-linear time limiter (Section 2.2, eqs. (27)-(29)).  Weight of one reconstruction:
+//   a1 = 1 + (tau_Z / (beta_min + eps))^2,  a2 = 1 + (tau_Z / (beta_max + eps))^2,
+//   alpha = 2 a2 / (a1 + a2)  (in (0, 1]: 1 on smooth data, -> 0 across a jump),
+// beta_min, beta_max over the four indicators of eq. (38), tau_Z of eq. (37).
+// ------------------------------------------------------------------------------------------------
+template <class real>
+DFW_HD real time_limiter_weight(const real* Q, const Coef<real>& k) {
+  real b[4];
+  weno_indicators(Q, b);
+  const real tau = (fabs(b[3] - b[0]) + fabs(b[3] - b[1]) + fabs(b[3] - b[2])) * real(1.0 / 3.0);
+  real bmin = b[0] < b[1] ? b[0] : b[1], bmax = b[0] > b[1] ? b[0] : b[1];
+  bmin = bmin < b[2] ? bmin : b[2];
+  bmin = bmin < b[3] ? bmin : b[3];
+  bmax = bmax > b[2] ? bmax : b[2];
+  bmax = bmax > b[3] ? bmax : b[3];
+  const real x1 = tau / (bmin + k.eps), x2 = tau / (bmax + k.eps);
+  const real a1 = real(1) + x1 * x1, a2 = real(1) + x2 * x2;
+  return real(2) * a2 / (a1 + a2);
+}
+
+// Weight omega of an interface: the smallest weight over the characteristic components of the two
+// normal reconstructions beside it (cells 2 and 3 of its six-cell row, each with its own stencil).
+template <class real>
+DFW_HD real time_limiter_omega(const real (*cell)[4], const Coef<real>& k) {
+  Basis<real> B = make_basis(cell[2], cell[3], k);
+  real Q[6][4];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) project(B, cell[m], Q[m]);
+  real om = real(1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    real sl[5], sr[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      sl[m] = Q[m][c];
+      sr[m] = Q[m + 1][c];
+    }
+    const real wl = time_limiter_weight(sl, k), wr = time_limiter_weight(sr, k);
+    om = om < wl ? om : wl;
+    om = om < wr ? om : wr;
+  }
+  return om;
 }
 
 // ------------------------------------------------------------------------------------------------

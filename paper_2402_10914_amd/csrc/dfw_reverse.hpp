@@ -659,7 +659,7 @@ static dfw_status adjoint_impl(const dfw_grid* g, const dfw_params* p, int nstep
       timed(DFW_K_FACES1, st, [&] { launch_faces<real>(FL, Wn(l), An(l), FX, FY, st); });
       timed(DFW_K_UPDATE1, st, [&] {
         hipLaunchKernelGGL(k_update1<real>, dim3(nb), dim3(kCellBlock), 0, st, Wn(l), FX, FY, Wss(l), R, ctrl, G,
-                           nullptr, nullptr, n);
+                           nullptr, nullptr, n, 0);
       });
       FL.out = OUT_FT | OUT_DF;
       timed(DFW_K_FACES2, st, [&] { launch_faces<real>(FL, Wss(l), An(l), FX, FY, st); });

@@ -50,16 +50,20 @@ struct GridDesc {
   double dx, dy, inv_dx, inv_dy;
   long long w_off;   // W, W*, R: [4][ny][nx] at this offset
   long long a_off;   // alpha: [ny][nx]
-  long long fx_off;  // x-interface data: [9][ny][nx+1]
-  long long fy_off;  // y-interface data: [9][ny+1][nx]
+  long long fx_off;  // x-interface data: [kFacePlanes][ny][nx+1]
+  long long fy_off;  // y-interface data: [kFacePlanes][ny+1][nx]
 };
 
 struct Scheme {
   double gamma, cfl, dt_fixed, alpha_thres, eps, c1, c2, K;
   double d[4];
+  int tl;  // non-linear time limiter (eqs. (27)-(29)) on
 };
 
-enum { OUT_F = 1, OUT_FT = 2, OUT_DF = 4 };
+// OUT_OMEGA: time-limiter weight of each interface: with OUT_F (first stage) stored in plane 9, without
+// (second stage) applied to the stored time derivative.
+enum { OUT_F = 1, OUT_FT = 2, OUT_DF = 4, OUT_OMEGA = 8 };
+constexpr int kFacePlanes = 10;  // F (4), dF/dt (4), DF product, time-limiter weight
 
 template <class real>
 __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
@@ -91,7 +95,7 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc) {
 // ------------------------------------------------------------------------------------------------
 // Interface kernel.
 // Interface data: entries 0..3 = face-averaged flux (global components), 4..7 = its time
-// derivative, 8 = product of the DF of the two Gauss points.
+// derivative, 8 = product of the DF of the two Gauss points, 9 = time-limiter weight.
 // Tile entry (batch form): x = grid, y = dir | (lead tile of its grid) << 1, z = f0, w = t0.
 // ------------------------------------------------------------------------------------------------
 template <int TF, int TR>
@@ -249,6 +253,15 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   real Fs[4], Fts[4], dfp;
   segment_fluxes<real, FLUX, (OUT & OUT_F) != 0, (OUT & OUT_DF) != 0>(wa, wb, line, al, wln, wrn, dt, inv_dt, k, Fs,
                                                                         Fts, dfp);
+  real om = real(1);
+  if (OUT & OUT_OMEGA) {  // eq. (29), from the six cells of this segment's row
+    real cell[6][4];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][rr][fl + m];
+    om = time_limiter_omega(cell, k);
+  }
   // ---- write face sums (quadrature weights 1/2), components back to the global order
   const size_t fstride = dir == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
   real* Fo = dir == 0 ? FX + (size_t)t * (nx + 1) + f : FY + (size_t)f * nx + t;
@@ -256,9 +269,13 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (OUT & OUT_F) Fo[cmap[c] * fstride] = real(0.5) * Fs[c];
-    if (OUT & OUT_FT) Fo[(4 + cmap[c]) * fstride] = real(0.5) * Fts[c];
+    if (OUT & OUT_FT) {
+      const real ft = real(0.5) * Fts[c];
+      Fo[(4 + cmap[c]) * fstride] = ((OUT & OUT_OMEGA) && !(OUT & OUT_F)) ? om * ft : ft;
+    }
   }
   if (OUT & OUT_DF) Fo[8 * fstride] = dfp;
+  if ((OUT & OUT_OMEGA) && (OUT & OUT_F)) Fo[9 * fstride] = om;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -310,12 +327,33 @@ __device__ __forceinline__ void face_sum(const real* FX, const real* FY, const G
   }
 }
 
+// The time derivative of eq. (28): each face's dL/dt weighted by its time-limiter weight (plane 9).
+template <class real>
+__device__ __forceinline__ void face_sum_limited(const real* FX, const real* FY, const GridDesc& G, int i, int j,
+                                                 real* out) {
+#pragma clang fp contract(off)
+  const int nx = G.nx, ny = G.ny;
+  const size_t sx = (size_t)ny * (nx + 1), sy = (size_t)(ny + 1) * nx;
+  const size_t w = (size_t)j * (nx + 1) + i, s = (size_t)j * nx + i;
+  const real ix = real(G.inv_dx), iy = real(G.inv_dy);
+  const real* ox = FX + 9 * sx;
+  const real* oy = FY + 9 * sy;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const real* fx = FX + (4 + c) * sx;
+    const real* fy = FY + (4 + c) * sy;
+    real ax = (ox[w] * fx[w] - ox[w + 1] * fx[w + 1]) * ix;
+    real ay = (oy[s] * fy[s] - oy[s + nx] * fy[s + nx]) * iy;
+    out[c] = ax + ay;
+  }
+}
+
 template <class real>
 __global__ __launch_bounds__(kCellBlock) void k_update1(const real* __restrict__ Wall, const real* __restrict__ FXall,
                                                         const real* __restrict__ FYall, real* __restrict__ Wsall,
                                                         real* __restrict__ Rall, Ctrl* __restrict__ ctrls, GridDesc G0,
                                                         const GridDesc* __restrict__ grids,
-                                                        const int2* __restrict__ cblocks, int step) {
+                                                        const int2* __restrict__ cblocks, int step, int tl) {
   const CellCtx C = cell_ctx(G0, grids, cblocks);
   Ctrl* ctrl = ctrls + C.gi;
   if (ctrl->fail_at <= step || !C.live) return;
@@ -330,6 +368,18 @@ __global__ __launch_bounds__(kCellBlock) void k_update1(const real* __restrict__
   face_sum(FXall + G.fx_off, FYall + G.fy_off, G, i, j, 0, L);
   face_sum(FXall + G.fx_off, FYall + G.fy_off, G, i, j, 4, Lt);
   const real h1 = real(0.5) * dt, h2 = dt * dt * real(0.125), r2 = dt * dt * real(1.0 / 6.0);
+  if (tl) {  // eq. (27): R = W + dt L + dt^2/2 L_t - dt^2/3 ~L_t (W* as without the limiter)
+    real Ltl[4];
+    face_sum_limited(FXall + G.fx_off, FYall + G.fy_off, G, i, j, Ltl);
+    const real q2 = dt * dt * real(0.5), q3 = dt * dt * real(1.0 / 3.0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      real w = W[c * N + o];
+      Ws[c * N + o] = w + h1 * L[c] + h2 * Lt[c];
+      R[c * N + o] = w + dt * L[c] + q2 * Lt[c] - q3 * Ltl[c];
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     real w = W[c * N + o];
@@ -567,6 +617,9 @@ template <class real>
 static void launch_faces(const FaceLaunch& L, const real* W, const real* A, real* FX, real* FY, hipStream_t st) {
   if (L.out == (OUT_F | OUT_FT)) launch_faces_out<real, OUT_F | OUT_FT>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_FT | OUT_DF)) launch_faces_out<real, OUT_FT | OUT_DF>(L, W, A, FX, FY, st);
+  else if (L.out == (OUT_F | OUT_FT | OUT_OMEGA)) launch_faces_out<real, OUT_F | OUT_FT | OUT_OMEGA>(L, W, A, FX, FY, st);
+  else if (L.out == (OUT_FT | OUT_DF | OUT_OMEGA))
+    launch_faces_out<real, OUT_FT | OUT_DF | OUT_OMEGA>(L, W, A, FX, FY, st);
   else launch_faces_out<real, OUT_F | OUT_FT | OUT_DF>(L, W, A, FX, FY, st);
 }
 
@@ -584,9 +637,9 @@ static WsLayout layout(const dfw_grid* g, size_t es) {
   L.r_off = off;
   off = align256(off + 4 * N * es);
   L.fx_off = off;
-  off = align256(off + 9 * (size_t)g->ny * (g->nx + 1) * es);
+  off = align256(off + kFacePlanes * (size_t)g->ny * (g->nx + 1) * es);
   L.fy_off = off;
-  off = align256(off + 9 * (size_t)(g->ny + 1) * g->nx * es);
+  off = align256(off + kFacePlanes * (size_t)(g->ny + 1) * g->nx * es);
   L.ctrl_off = off;
   off = align256(off + sizeof(Ctrl));
   L.total = off;
@@ -612,6 +665,7 @@ static dfw_status check_params(const dfw_params* p, int32_t dtype) {
   if (!(p->eps_weno > 0)) return fail(DFW_EINVAL, "eps_weno must be > 0");
   if (!(p->c1 >= 0) || !(p->c2 >= 0)) return fail(DFW_EINVAL, "c1, c2 must be >= 0");
   if (p->tile < 0 || p->tile >= kNumShapes) return fail(DFW_EINVAL, "tile must be in [0, dfw_num_tiles())");
+  if (p->time_limiter != 0 && p->time_limiter != 1) return fail(DFW_EINVAL, "time_limiter must be 0 or 1");
   if (dtype != DFW_F64 && dtype != DFW_F32) return fail(DFW_EDTYPE, "dtype must be DFW_F64 or DFW_F32");
   return DFW_OK;
 }
@@ -635,6 +689,7 @@ static Scheme make_scheme(const dfw_params* p) {
   S.d[0] = (1.0 - p->d_h) * (1.0 - p->d_l) / 2.0;
   S.d[1] = (1.0 - p->d_h) * p->d_l;
   S.d[2] = S.d[0];
+  S.tl = p->time_limiter;
   return S;
 }
 
@@ -692,15 +747,15 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
   for (int n = 0; n < nsteps; ++n) {
     before_step(n);
     L.step = n;
-    L.out = OUT_F | OUT_FT;
+    L.out = OUT_F | OUT_FT | (S.tl ? OUT_OMEGA : 0);
     L.lead = 1;
     L.dt_hist = dt_hist;
     timed(DFW_K_FACES1, st, [&] { launch_faces<real>(L, W, A, FX, FY, st); });
     timed(DFW_K_UPDATE1, st, [&] {
       hipLaunchKernelGGL(k_update1<real>, dim3(nb), dim3(kCellBlock), 0, st, W, FX, FY, Ws, R, ctrls, G0, grids,
-                         cblocks, n);
+                         cblocks, n, S.tl);
     });
-    L.out = OUT_FT | OUT_DF;
+    L.out = OUT_FT | OUT_DF | (S.tl ? OUT_OMEGA : 0);
     L.lead = 0;
     L.dt_hist = nullptr;
     timed(DFW_K_FACES2, st, [&] { launch_faces<real>(L, Ws, A, FX, FY, st); });
@@ -947,8 +1002,8 @@ dfw_status dfw_batch_plan(const dfw_grid* grids, int32_t ngrids, const dfw_param
     G.fy_off = (long long)b->fy_elems;
     b->w_elems += 4 * N;
     b->a_elems += N;
-    b->fx_elems += 9 * (size_t)G.ny * (G.nx + 1);
-    b->fy_elems += 9 * (size_t)(G.ny + 1) * G.nx;
+    b->fx_elems += kFacePlanes * (size_t)G.ny * (G.nx + 1);
+    b->fy_elems += kFacePlanes * (size_t)(G.ny + 1) * G.nx;
     b->grids.push_back(G);
     const size_t ncb = (N + kCellBlock - 1) / kCellBlock;
     for (size_t k = 0; k < ncb; ++k) b->cblocks.push_back(make_int2(g, (int)(k * kCellBlock)));
@@ -1117,6 +1172,7 @@ dfw_status dfw_adjoint(const dfw_grid* grid, const dfw_params* params, int32_t d
   dfw_status s = check_common(grid, params, dtype);
   if (s != DFW_OK) return s;
   if (dtype != DFW_F64) return fail(DFW_EDTYPE, "the adjoint is implemented in FP64 only");
+  if (params->time_limiter) return fail(DFW_EINVAL, "the adjoint does not cover the time limiter");
   if (!gW_final || !gW0) return fail(DFW_EINVAL, "gW_final and gW0 must be non-null");
   if (!dt_hist_dev && nsteps > 0) return fail(DFW_EINVAL, "dt_hist_dev is required");
   if ((s = check_ckpt(grid, dtype, nsteps, ckpt_every, ckpt, ckpt_bytes)) != DFW_OK) return s;

@@ -1,0 +1,101 @@
+"""The non-linear time limiter (Section 2.2, eqs. (27)-(29)) on the GPU against the oracle, through
+the C ABI: Riemann data (the limiter acts at every wave), LF and GKS, FP64 and FP32; conservation
+on a periodic grid; the batched form bitwise equal to the per-grid loop with the limiter on.
+
+The limited step map amplifies rounding-level differences: next to a jump the ratio tau/(beta+eps)
+of eq. (29) is of order one, where the weight moves fast with the data, and the oracle run from an
+input perturbed by one ulp drifts from its own unperturbed run by ~1e-12 (rel-L1) after ten LF
+steps, while without the limiter the drift stays ~5e-16.  Parity is therefore checked step by step
+from the oracle's own states along a ten-step trajectory, and over a whole trajectory only as long
+as that drift stays far below the FP64 bar (five steps)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2402_10914_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2402_10914_amd import api
+    return api
+
+
+def _rel_l1_rows(a, b):
+    return max(float(np.abs(a[c] - b[c]).sum() / np.abs(b[c]).sum()) for c in range(a.shape[0]))
+
+
+def _gpu_run(pr, flux, nsteps, dtype=torch.float64, time_limiter=1, cfl=0.4, W0=None, A0=None):
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, cfl=cfl, time_limiter=time_limiter), dtype)
+    W = torch.tensor(pr.W if W0 is None else W0, dtype=dtype, device="cuda")
+    A = torch.tensor(pr.alpha if A0 is None else A0, dtype=dtype, device="cuda")
+    dth = torch.zeros(nsteps, dtype=torch.float64, device="cuda")
+    t, fs = st.run(W, A, nsteps, dt_hist=dth)
+    return W.double().cpu().numpy(), A.double().cpu().numpy(), dth.cpu().numpy(), fs
+
+
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+def test_limited_run_matches_oracle(flux):
+    pr = WL.riemann4(48, 40, seed=48)
+    W, A, dth, fs = _gpu_run(pr, flux, 5)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    Wo, Ao, _, dto, fso = O.run(pr.W, pr.alpha, g, O.make_params(flux=flux, cfl=0.4, time_limiter=1), 5)
+    assert fs == -1 and fso == -1
+    assert _rel_l1_rows(W, Wo) <= 1e-12
+    assert np.abs(A - Ao).sum() / np.abs(Ao).sum() <= 1e-12
+    np.testing.assert_allclose(dth, dto, rtol=1e-12)
+    # the limiter changed the result (it acts at the waves)
+    Wu, _, _, _ = _gpu_run(pr, flux, 5, time_limiter=0)
+    assert _rel_l1_rows(W, Wu) > 1e-9
+
+
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+def test_limited_step_matches_oracle_along_trajectory(flux):
+    pr = WL.riemann4(48, 40, seed=48)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    P = O.make_params(flux=flux, cfl=0.4, time_limiter=1)
+    Wk, Ak = pr.W, pr.alpha
+    for k in range(10):
+        Wn, An, _, dto, fso = O.run(Wk, Ak, g, P, 1)
+        W, A, dth, fs = _gpu_run(pr, flux, 1, W0=Wk, A0=Ak)
+        assert fs == -1 and fso == -1, k
+        assert _rel_l1_rows(W, Wn) <= 1e-12, k
+        assert np.abs(A - An).sum() / np.abs(An).sum() <= 1e-12, k
+        np.testing.assert_allclose(dth, dto, rtol=1e-12)
+        Wk, Ak = Wn, An
+
+
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+def test_limited_run_fp32_matches_oracle(flux):
+    pr = WL.riemann4(40, 36, seed=36)
+    W, A, dth, fs = _gpu_run(pr, flux, 6, dtype=torch.float32)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    Wo, Ao, _, _, fso = O.run(pr.W, pr.alpha, g, O.make_params(flux=flux, cfl=0.4, dt_fixed=0.0, time_limiter=1), 6)
+    assert fs == -1 and fso == -1
+    assert _rel_l1_rows(W, Wo) <= 1e-5
+
+
+def test_limited_periodic_run_conserves():
+    pr = WL.riemann4(64, 64, seed=64)
+    pr.bc_x = pr.bc_y = WL.BC_PERIODIC
+    W, _, _, fs = _gpu_run(pr, WL.FLUX_GKS, 20)
+    assert fs == -1
+    s0, s1 = pr.W.sum(axis=(1, 2)), W.sum(axis=(1, 2))
+    assert np.all(np.abs(s1 - s0) <= 1e-12 * np.abs(W).sum(axis=(1, 2)))
+
+
+def test_limited_batch_equals_loop_bitwise():
+    api = _api()
+    rng = np.random.default_rng(5)
+    probs = [WL.riemann4(int(a), int(b), seed=[5, g]) for g, (a, b) in enumerate(rng.integers(8, 60, (6, 2)))]
+    params = api.Params(flux=api.FLUX_GKS, cfl=0.4, time_limiter=1)
+    b = api.Batch([(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y) for p in probs], params, torch.float64, 0)
+    W, A = b.pack([p.W for p in probs], [p.alpha for p in probs])
+    _, fs = b.run(W, A, 8, use_graph=True)
+    for p, (w, a), f in zip(probs, b.unpack(W, A), fs):
+        Wl, Al, _, fl = _gpu_run(p, api.FLUX_GKS, 8)
+        assert f == fl
+        assert np.array_equal(w.cpu().numpy(), Wl) and np.array_equal(a.cpu().numpy(), Al)

@@ -675,3 +675,20 @@ def test_limited_density_wave_matches_unlimited_closely():
     Wa, _, _, _, _ = O.run(pr.W, pr.alpha, g, O.make_params(cfl=0.5), 10)
     Wb, _, _, _, _ = O.run(pr.W, pr.alpha, g, O.make_params(cfl=0.5, time_limiter=1), 10)
     assert np.abs(Wa - Wb).max() <= 1e-10
+
+
+def test_limited_map_amplifies_rounding_unlike_eq21():
+    """Conditioning of the limited step (eqs. (27)-(29)) on Riemann data, which fixes how its GPU
+    parity is checked: a one-ulp perturbation of the input grows to well above rounding level in
+    ten LF steps with the limiter, and stays at rounding level with eq. (21)."""
+    pr = WL.riemann4(48, 40, seed=48)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    Wp = pr.W * (1 + 2.2e-16 * np.random.default_rng(1).choice([-1, 1], pr.W.shape))
+    drift = {}
+    for tl in (0, 1):
+        P = O.make_params(flux=O.FLUX_LF, cfl=0.4, time_limiter=tl)
+        a = O.run(pr.W, pr.alpha, g, P, 10)[0]
+        b = O.run(Wp, pr.alpha, g, P, 10)[0]
+        drift[tl] = np.abs(a - b).sum() / np.abs(a).sum()
+    assert drift[0] <= 2e-15
+    assert drift[1] >= 1e-14
