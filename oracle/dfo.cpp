@@ -27,6 +27,8 @@
  *   (R9) the normal derivative at a Gauss point is the line value of the normal sweep.
  *   (R13) transmissive boundary = copy of the nearest interior cell.
  *   (R24) second-stage GKS integrals use the same dt and tau_n formula as the first stage.
+ *   (R29) SSP-RK3 (eq. (32)): dt from the CFL condition on W^n, alpha^n in all three stages,
+ *        alpha^{n+1} from the Gauss-point states of the third stage.
  * Functions that are not pinned by a closed form, a special case or brute force say so.
  */
 #include <algorithm>
@@ -116,6 +118,7 @@ struct Params {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
   int32_t time_limiter; /* 1: eqs. (27)-(29) for the second-stage update */
+  int32_t time_scheme;  /* 0: S2O4, eq. (21); 1: SSP-RK3, eq. (32) */
 };
 
 /* ------------------------------------------------------------------------------------------ */
@@ -987,6 +990,40 @@ static void s2o4_step(T* W, T* alpha, const Grid& G, const Params& prm, double d
   for (size_t k = 0; k < N; ++k) alpha[k] = an[k];
 }
 
+/* Section 2.3, eq. (32), SSP-RK3 in the paper's (expanded) form:
+ *   W1 = W^n + dt L(W^n),
+ *   W2 = 3/4 W^n + 1/4 W1 + 1/4 dt L(W1),
+ *   W^{n+1} = 1/3 W^n + 2/3 W2 + 2/3 dt L(W2).
+ * op(W, L, stage) evaluates the operator of stage 0, 1 or 2. */
+template <class T, class Op>
+static void ssprk3(T* W, size_t n, double dt, Op op) {
+  std::vector<T> L(n), W1(n), W2(n);
+  op(W, L.data(), 0);
+  for (size_t k = 0; k < n; ++k) W1[k] = W[k] + dt * L[k];
+  op(W1.data(), L.data(), 1);
+  for (size_t k = 0; k < n; ++k) W2[k] = 0.75 * W[k] + 0.25 * W1[k] + 0.25 * dt * L[k];
+  op(W2.data(), L.data(), 2);
+  for (size_t k = 0; k < n; ++k) W[k] = (1.0 / 3.0) * W[k] + (2.0 / 3.0) * W2[k] + (2.0 / 3.0) * dt * L[k];
+}
+
+template <class T>
+static void ssprk3_step(T* W, T* alpha, const Grid& G, const Params& prm, double dt) {
+  const size_t N = (size_t)G.nx * G.ny;
+  std::vector<T> an(N), Lt(4 * N);
+  ssprk3(W, 4 * N, dt, [&](const T* w, T* L, int stage) {
+    /* (R29) alpha^n in all stages; alpha^{n+1} from the third stage's Gauss points.  Only L enters
+     * eq. (32); the time derivative the operator also returns is discarded. */
+    spatial_operator(w, alpha, G, prm, dt, L, Lt.data(), stage == 2 ? an.data() : (T*)nullptr);
+  });
+  for (size_t k = 0; k < N; ++k) alpha[k] = an[k];
+}
+
+template <class T>
+static void time_step(T* W, T* alpha, const Grid& G, const Params& prm, double dt) {
+  if (prm.time_scheme == 1) ssprk3_step(W, alpha, G, prm, dt);
+  else s2o4_step(W, alpha, G, prm, dt);
+}
+
 }  // namespace dfo
 
 /* ============================================================================================ */
@@ -1003,13 +1040,13 @@ struct dfo_grid {
 };
 struct dfo_params {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
-  int32_t flux, time_limiter;
+  int32_t flux, time_limiter, time_scheme;
 };
 
 static Grid to_grid(const dfo_grid* g) { return Grid{g->nx, g->ny, g->dx, g->dy, g->bc_x, g->bc_y}; }
 static Params to_params(const dfo_params* p) {
   return Params{p->gamma, p->cfl, p->dt_fixed, p->alpha_thres, p->d_h, p->d_l, p->eps_weno, p->c1, p->c2, p->flux,
-                p->time_limiter};
+                p->time_limiter, p->time_scheme};
 }
 
 /* 0 on success, 1 when the state holds a non-positive density/pressure or a non-finite value. */
@@ -1041,7 +1078,7 @@ int dfo_run(double* W, double* alpha, const dfo_grid* g, const dfo_params* p, in
       return 1;
     }
     double dt = P.dt_fixed > 0.0 ? P.dt_fixed : P.cfl / smax;
-    s2o4_step(W, alpha, G, P, dt);
+    time_step(W, alpha, G, P, dt);
     if (dt_hist) dt_hist[n] = dt;
     t += dt;
   }
@@ -1067,7 +1104,7 @@ void dfo_run_tangent(double* W, double* alpha, double* dW, double* dalpha, const
   std::vector<Dual<double>> w(4 * N), a(N);
   for (size_t k = 0; k < 4 * N; ++k) w[k] = Dual<double>(W[k], dW[k]);
   for (size_t k = 0; k < N; ++k) a[k] = Dual<double>(alpha[k], dalpha[k]);
-  for (int n = 0; n < nsteps; ++n) s2o4_step(w.data(), a.data(), G, P, dt_hist[n]);
+  for (int n = 0; n < nsteps; ++n) time_step(w.data(), a.data(), G, P, dt_hist[n]);
   for (size_t k = 0; k < 4 * N; ++k) {
     W[k] = w[k].v;
     dW[k] = w[k].d;
@@ -1116,6 +1153,12 @@ double dfo_s2o4_scalar(double u, double lam, double dt) {
     L[0] = lam * w[0];
     Lt[0] = lam * lam * w[0];
   });
+  return u;
+}
+
+/* One SSP-RK3 step of the scalar ODE u' = lam u. */
+double dfo_ssprk3_scalar(double u, double lam, double dt) {
+  ssprk3(&u, 1, dt, [&](const double* w, double* L, int) { L[0] = lam * w[0]; });
   return u;
 }
 

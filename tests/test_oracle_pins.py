@@ -692,3 +692,101 @@ def test_limited_map_amplifies_rounding_unlike_eq21():
         drift[tl] = np.abs(a - b).sum() / np.abs(a).sum()
     assert drift[0] <= 2e-15
     assert drift[1] >= 1e-14
+
+
+# ----------------------------------------------------------------------------------------------
+# Section 2.3: SSP-RK3 (eq. (32)) with the LF flux
+# ----------------------------------------------------------------------------------------------
+
+def test_ssprk3_is_third_order_taylor_on_linear_ode():
+    """On u' = lam u one step of eq. (32) is the cubic Taylor polynomial of exp(lam dt)."""
+    import ctypes
+    L = O.lib()
+    L.dfo_ssprk3_scalar.restype = ctypes.c_double
+    L.dfo_ssprk3_scalar.argtypes = [ctypes.c_double] * 3
+    for z in (0.3, -0.7, 1.1, -2.0):
+        got = L.dfo_ssprk3_scalar(1.0, z, 1.0)
+        assert got == pytest.approx(1 + z + z * z / 2 + z ** 3 / 6, rel=1e-15, abs=1e-15)
+
+
+def test_ssprk3_temporal_order_three_on_euler_path():
+    """Fixed 32x32 mesh, density wave, LF, T = 0.4: halving dt shrinks the change of the solution
+    by 2^3 (a wrong stage coefficient drops the order); DF stays 1 (a pure entropy wave)."""
+    pr = WL.density_wave(32)
+    g = O.make_grid(32, 32, pr.dx, pr.dy)
+    sols = []
+    for ns in (40, 80, 160):
+        p = O.make_params(flux=O.FLUX_LF, dt_fixed=0.4 / ns, time_scheme=O.TIME_SSPRK3)
+        W, a, _, _, fs = O.run(pr.W, pr.alpha, g, p, ns)
+        assert fs == -1
+        assert np.all(np.abs(a - 1.0) <= 1e-12)
+        sols.append(W)
+    d1 = np.abs(sols[0] - sols[1]).sum()
+    d2 = np.abs(sols[1] - sols[2]).sum()
+    assert 2.85 <= math.log2(d1 / d2) <= 3.15
+
+
+def test_paper_table2_ssprk3_lf():
+    """Section 4.1 Table 2 (1-D, LF, SSP-RK3, t = 2).  The printed errors are the spatial error of the
+    scheme: at the stated dt = 0.25 dx the third-order temporal error alone (pi^4 dt^3 / 12 of the
+    amplitude over the run) exceeds them from 80 cells on.  With dt = dx / 16 the oracle reproduces
+    them within 5 %; at dt = 0.25 dx the 20-cell error is within 25 %."""
+    tab = _gold("paper_accuracy_tables.json")["table2"]
+
+    def err(n, frac):
+        pr = WL.sine_wave_1d(n)
+        g = O.make_grid(n, 1, pr.dx, pr.dy)
+        ns = int(round(2.0 / (frac * pr.dx)))
+        p = O.make_params(flux=O.FLUX_LF, dt_fixed=2.0 / ns, time_scheme=O.TIME_SSPRK3)
+        W, _, t, _, fs = O.run(pr.W, pr.alpha, g, p, ns)
+        assert fs == -1
+        return np.abs(W[0, 0] - WL.sine_wave_1d_avg(n, t)).mean()
+
+    for n, ref in zip(tab["n"][:3], tab["l1"][:3]):
+        e = err(n, 1.0 / 16)
+        assert abs(e / ref - 1) <= 0.05, (n, e, ref)
+    e = err(20, 0.25)
+    assert abs(e / tab["l1"][0] - 1) <= 0.25
+
+
+def test_paper_table4_ssprk3_lf_soft():
+    """Section 4.1 Table 4 (2-D product wave, LF, SSP-RK3, CFL 0.1): 20x20 within a factor 3."""
+    tab = _gold("paper_accuracy_tables.json")["table4"]
+    n, ref = tab["n"][0], tab["l1"][0]
+    pr = WL.product_wave(n)
+    g = O.make_grid(n, n, pr.dx, pr.dy)
+    smax, _ = O.max_speed(pr.W, g, O.make_params())
+    ns = int(math.ceil(2.0 / (0.1 / smax)))
+    p = O.make_params(flux=O.FLUX_LF, dt_fixed=2.0 / ns, time_scheme=O.TIME_SSPRK3)
+    W, _, t, _, _ = O.run(pr.W, pr.alpha, g, p, ns)
+    e = np.abs(W[0] - WL.product_wave_avg(n, t)).mean()
+    assert ref / 3 <= e <= 3 * ref, (e, ref)
+
+
+def test_ssprk3_conservation_symmetry_positivity():
+    """Periodic conservation (each stage is a convex combination of conservative updates), the
+    x <-> y transpose symmetry, and positivity with DF in [0, 1] on Riemann data."""
+    p = O.make_params(flux=O.FLUX_LF, cfl=0.4, time_scheme=O.TIME_SSPRK3)
+    pr = WL.circles(64, ncirc=6, flux=O.FLUX_LF)
+    g = O.make_grid(64, 64, pr.dx, pr.dy)
+    W, _, _, _, fs = O.run(pr.W, pr.alpha, g, p, 4)
+    assert fs == -1
+    for c in range(4):
+        assert abs(W[c].sum() - pr.W[c].sum()) <= 1e-13 * max(1.0, np.abs(pr.W[c]).sum())
+    pr, g, _ = _riemann_small(flux=O.FLUX_LF, steps=3)
+    W0 = pr.W
+    Wt = np.stack([W0[0].T, W0[2].T, W0[1].T, W0[3].T]).copy()
+    A, aa, _, _, _ = O.run(W0, pr.alpha, g, p, 3)
+    B, ab, _, _, _ = O.run(Wt, pr.alpha.T.copy(), g, p, 3)
+    Bt = np.stack([B[0].T, B[2].T, B[1].T, B[3].T])
+    np.testing.assert_allclose(Bt, A, rtol=0, atol=1e-13 * np.abs(A).max())
+    np.testing.assert_allclose(ab.T, aa, rtol=0, atol=1e-13)
+    W, a, _, _, fs = O.run(W0, pr.alpha, g, p, 20)
+    assert fs == -1
+    rho = W[0]
+    pres = 0.4 * (W[3] - 0.5 * (W[1] ** 2 + W[2] ** 2) / rho)
+    assert rho.min() > 0 and pres.min() > 0
+    assert a.min() >= 0 and a.max() <= 1
+    # the SSP-RK3 result differs from S2O4 on the same data
+    Ws, _, _, _, _ = O.run(W0, pr.alpha, g, O.make_params(flux=O.FLUX_LF, cfl=0.4), 20)
+    assert np.abs(Ws - W).max() > 1e-6
