@@ -41,6 +41,7 @@ typedef enum {
 enum { DFW_FLUX_LF = 0, DFW_FLUX_GKS = 1 };        /* Section 2.3 (Lax-Friedrichs), Section 2.2 (gas-kinetic) */
 enum { DFW_BC_PERIODIC = 0, DFW_BC_TRANSMISSIVE = 1 };
 enum { DFW_F64 = 0, DFW_F32 = 1 };
+enum { DFW_TIME_S2O4 = 0, DFW_TIME_SSPRK3 = 1 };  /* eq. (21) (Section 2.2), eq. (32) (Section 2.3) */
 
 /* Uniform structured grid: nx by ny cells of size dx by dy; one boundary type per axis.
  * Transmissive = ghost cells copy the nearest interior cell ("free" boundary of the paper). */
@@ -62,18 +63,27 @@ typedef struct {
  *   tile         interface tile shape, 0 <= tile < dfw_num_tiles() [0]; results do not depend on it
  *   time_limiter 1: the non-linear time limiter of Section 2.2 (eqs. (27)-(29)) for the second-stage
  *                update; 0: plain eq. (21) [0].  The limiter's epsilon is eps_weno.  dfw_rhs
- *                returns the unlimited dL/dt; dfw_adjoint rejects time_limiter = 1. */
+ *                returns the unlimited dL/dt; dfw_adjoint rejects time_limiter = 1.
+ *   time_scheme  DFW_TIME_S2O4: the two-stage fourth-order step of eq. (21) [default];
+ *                DFW_TIME_SSPRK3: the three-stage SSP Runge-Kutta step of eq. (32), which needs no
+ *                flux time derivative.  As in the paper it runs with the LF flux only (GKS, or
+ *                the time limiter, with it are rejected with DFW_EINVAL).  dt comes from the CFL
+ *                condition on W^n, alpha^n drives the hybrid switch in all three stages and
+ *                alpha^{n+1} is built from the third stage's Gauss points.  dfw_adjoint covers
+ *                DFW_TIME_S2O4 only. */
 typedef struct {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
   int32_t tile;
   int32_t time_limiter;
+  int32_t time_scheme;
 } dfw_params;
 
 /* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */
 size_t dfw_workspace_bytes(const dfw_grid* grid, int32_t dtype);
 
-/* Advance (W, alpha) in place by nsteps S2O4 steps (eq. (21); Algorithm 1).
+/* Advance (W, alpha) in place by nsteps time steps: S2O4 (eq. (21); Algorithm 1), or SSP-RK3
+ * (eq. (32)) when params->time_scheme says so.
  *   W, alpha        device, in/out.
  *   dt_hist_dev     device, optional (may be NULL): receives the nsteps time increments (FP64).
  *   t_out           host, optional: sum of the time increments actually taken.
@@ -184,7 +194,9 @@ enum {
   DFW_K_ADJ_FACES1 = 6, /* adjoint interface kernel, first stage */
   DFW_K_ADJ_FACES2 = 7, /* adjoint interface kernel, second stage */
   DFW_K_ADJ_GATHER = 8, /* adjoint cell gather (both stages) */
-  DFW_K_COUNT = 9
+  DFW_K_RK_FACES = 9,   /* interface kernel of an SSP-RK3 stage (flux; DF in the third stage) */
+  DFW_K_RK_UPDATE = 10, /* cell kernel of an SSP-RK3 stage (the third with alpha^{n+1} and CFL reduction) */
+  DFW_K_COUNT = 11
 };
 
 /* enable != 0 clears the records and starts recording; 0 stops.  Process-wide, not thread-safe;

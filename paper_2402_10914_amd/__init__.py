@@ -10,7 +10,7 @@ Attributes that need torch are imported lazily so that the input generators work
 """
 
 _API = {"Stepper", "Params", "Batch", "Adjoint", "Rollout", "rollout", "KernelProfile", "tile_shapes", "run", "FLUX_LF",
-        "FLUX_GKS", "BC_PERIODIC", "BC_TRANSMISSIVE", "DFWError"}
+        "FLUX_GKS", "TIME_S2O4", "TIME_SSPRK3", "BC_PERIODIC", "BC_TRANSMISSIVE", "DFWError"}
 
 
 def __getattr__(name):

@@ -14,10 +14,11 @@ LIB_PATH = os.path.join(HERE, "libdfweno.so")
 
 DFW_OK, DFW_EINVAL, DFW_EDTYPE, DFW_EWORKSPACE, DFW_EHIP, DFW_ENONPHYS = range(6)
 DFW_FLUX_LF, DFW_FLUX_GKS = 0, 1
+DFW_TIME_S2O4, DFW_TIME_SSPRK3 = 0, 1
 DFW_BC_PERIODIC, DFW_BC_TRANSMISSIVE = 0, 1
 DFW_F64, DFW_F32 = 0, 1
 KERNEL_KINDS = ["faces1", "update1", "faces2", "update2", "speed", "graph", "adj_faces1", "adj_faces2",
-                "adj_gather"]
+                "adj_gather", "rk_faces", "rk_update"]
 DFW_ORDER_GRID, DFW_ORDER_LARGEST_FIRST, DFW_ORDER_INTERLEAVED = 0, 1, 2
 
 
@@ -30,7 +31,8 @@ class dfw_params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
                 ("alpha_thres", ctypes.c_double), ("d_h", ctypes.c_double), ("d_l", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
-                ("flux", ctypes.c_int32), ("tile", ctypes.c_int32), ("time_limiter", ctypes.c_int32)]
+                ("flux", ctypes.c_int32), ("tile", ctypes.c_int32), ("time_limiter", ctypes.c_int32),
+                ("time_scheme", ctypes.c_int32)]
 
 
 class DFWError(RuntimeError):

@@ -15,9 +15,10 @@ import torch
 
 from . import _lib
 from ._lib import (DFW_BC_PERIODIC, DFW_BC_TRANSMISSIVE, DFW_ENONPHYS, DFW_F32, DFW_F64, DFW_FLUX_GKS,
-                   DFW_FLUX_LF, DFW_OK, DFWError)
+                   DFW_FLUX_LF, DFW_OK, DFW_TIME_S2O4, DFW_TIME_SSPRK3, DFWError)
 
 FLUX_LF, FLUX_GKS = DFW_FLUX_LF, DFW_FLUX_GKS
+TIME_S2O4, TIME_SSPRK3 = DFW_TIME_S2O4, DFW_TIME_SSPRK3
 BC_PERIODIC, BC_TRANSMISSIVE = DFW_BC_PERIODIC, DFW_BC_TRANSMISSIVE
 
 
@@ -36,11 +37,13 @@ class Params:
     c2: float = 5.0
     tile: int = 0  # interface tile shape (performance only; see tile_shapes())
     time_limiter: int = 0  # 1: non-linear time limiter of Section 2.2, eqs. (27)-(29)
+    time_scheme: int = TIME_S2O4  # TIME_SSPRK3: eq. (32) of Section 2.3 (LF flux only)
 
     def struct(self) -> _lib.dfw_params:
         return _lib.dfw_params(float(self.gamma), float(self.cfl), float(self.dt_fixed), float(self.alpha_thres),
                                float(self.d_h), float(self.d_l), float(self.eps_weno), float(self.c1),
-                               float(self.c2), int(self.flux), int(self.tile), int(self.time_limiter))
+                               float(self.c2), int(self.flux), int(self.tile), int(self.time_limiter),
+                               int(self.time_scheme))
 
 
 def tile_shapes():
@@ -104,7 +107,8 @@ class Stepper:
 
     def run(self, W: torch.Tensor, alpha: torch.Tensor, nsteps: int, dt_hist: torch.Tensor | None = None,
             params: Params | None = None, strict: bool = False):
-        """Advance (W, alpha) in place by nsteps S2O4 steps.  Returns (t, fail_step); fail_step is -1
+        """Advance (W, alpha) in place by nsteps time steps (S2O4, or SSP-RK3 when params.time_scheme
+        is TIME_SSPRK3).  Returns (t, fail_step); fail_step is -1
         unless a non-physical state was met (then W holds it; strict=True raises instead)."""
         self._check(W, alpha)
         if dt_hist is not None and (dt_hist.dtype != torch.float64 or dt_hist.numel() < nsteps

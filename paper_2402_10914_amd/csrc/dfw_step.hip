@@ -58,6 +58,7 @@ struct Scheme {
   double gamma, cfl, dt_fixed, alpha_thres, eps, c1, c2, K;
   double d[4];
   int tl;  // non-linear time limiter (eqs. (27)-(29)) on
+  int ts;  // time scheme: DFW_TIME_S2O4 (eq. (21)) or DFW_TIME_SSPRK3 (eq. (32))
 };
 
 // OUT_OMEGA: time-limiter weight of each interface: with OUT_F (first stage) stored in plane 9, without
@@ -429,6 +430,23 @@ __device__ __forceinline__ void block_reduce_commit(double s, int bad, Ctrl* ctr
   }
 }
 
+// Stores the new state w of cell (i, j), its alpha^{n+1} (product of the DF of its four faces,
+// Section 3.2) and returns whether the state is physical, with its signal speed in s.
+template <class real>
+__device__ __forceinline__ int finish_cell(const real* w, real* W, real* Aall, const real* FX, const real* FY,
+                                           const GridDesc& G, const Scheme& S, size_t o, int i, int j, double& s) {
+  const size_t N = (size_t)G.nx * G.ny;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) W[c * N + o] = w[c];
+  const int nx = G.nx, ny = G.ny;
+  const size_t sx = (size_t)ny * (nx + 1), sy = (size_t)(ny + 1) * nx;
+  const size_t fw = (size_t)j * (nx + 1) + i;
+  const real* ax = FX + 8 * sx;
+  const real* ay = FY + 8 * sy;
+  Aall[G.a_off + o] = (ax[fw] * ax[fw + 1]) * (ay[o] * ay[o + nx]);
+  return cell_speed(w, S, G, s) ? 0 : 1;
+}
+
 template <class real>
 __global__ __launch_bounds__(kCellBlock) void k_update2(real* __restrict__ Wall, real* __restrict__ Aall,
                                                         const real* __restrict__ Rall, const real* __restrict__ FXall,
@@ -446,24 +464,76 @@ __global__ __launch_bounds__(kCellBlock) void k_update2(real* __restrict__ Wall,
     const int i = (int)(o % G.nx), j = (int)(o / G.nx);
     const real* FX = FXall + G.fx_off;
     const real* FY = FYall + G.fy_off;
-    real* W = Wall + G.w_off;
     const real* R = Rall + G.w_off;
     const real dt = real(ctrl->dt);
     real Lt[4], w[4];
     face_sum(FX, FY, G, i, j, 4, Lt);
     const real r3 = dt * dt * real(1.0 / 3.0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      w[c] = R[c * N + o] + r3 * Lt[c];
-      W[c * N + o] = w[c];
-    }
-    const int nx = G.nx, ny = G.ny;
-    const size_t sx = (size_t)ny * (nx + 1), sy = (size_t)(ny + 1) * nx;
-    const size_t fw = (size_t)j * (nx + 1) + i;
-    const real* ax = FX + 8 * sx;
-    const real* ay = FY + 8 * sy;
-    Aall[G.a_off + o] = (ax[fw] * ax[fw + 1]) * (ay[o] * ay[o + nx]);
-    bad = cell_speed(w, S, G, s) ? 0 : 1;
+    for (int c = 0; c < 4; ++c) w[c] = R[c * N + o] + r3 * Lt[c];
+    bad = finish_cell(w, Wall + G.w_off, Aall, FX, FY, G, S, o, i, j, s);
+  }
+  block_reduce_commit(s, bad, ctrl, (step + 1) & 1, step + 1);
+}
+
+// Eq. (32), SSP-RK3, first two stages, from the face fluxes of the stage state:
+//   STAGE 1: U = W^n + dt L(W^n);   STAGE 2: U = 3/4 W^n + 1/4 W1 + 1/4 dt L(W1).
+template <class real, int STAGE>
+__global__ __launch_bounds__(kCellBlock) void k_rk_stage(const real* __restrict__ Wall, const real* __restrict__ W1all,
+                                                         const real* __restrict__ FXall, const real* __restrict__ FYall,
+                                                         real* __restrict__ Uall, Ctrl* __restrict__ ctrls, GridDesc G0,
+                                                         const GridDesc* __restrict__ grids,
+                                                         const int2* __restrict__ cblocks, int step) {
+  const CellCtx C = cell_ctx(G0, grids, cblocks);
+  Ctrl* ctrl = ctrls + C.gi;
+  if (ctrl->fail_at <= step || !C.live) return;
+  const GridDesc& G = C.G;
+  const size_t N = (size_t)G.nx * G.ny, o = C.o;
+  const int i = (int)(o % G.nx), j = (int)(o / G.nx);
+  const real* W = Wall + G.w_off;
+  real* U = Uall + G.w_off;
+  const real dt = real(ctrl->dt);
+  real L[4];
+  face_sum(FXall + G.fx_off, FYall + G.fy_off, G, i, j, 0, L);
+  if (STAGE == 1) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[c * N + o] = W[c * N + o] + dt * L[c];
+  } else {
+    const real* W1 = W1all + G.w_off;
+    const real q = real(0.25) * dt;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[c * N + o] = (real(0.75) * W[c * N + o] + real(0.25) * W1[c * N + o]) + q * L[c];
+  }
+}
+
+// Eq. (32), third stage: W^{n+1} = 1/3 W^n + 2/3 W2 + 2/3 dt L(W2), with alpha^{n+1} from this stage's
+// Gauss points and the CFL reduction of the new state (as the second S2O4 stage).
+template <class real>
+__global__ __launch_bounds__(kCellBlock) void k_rk_final(real* __restrict__ Wall, real* __restrict__ Aall,
+                                                         const real* __restrict__ W2all, const real* __restrict__ FXall,
+                                                         const real* __restrict__ FYall, Ctrl* __restrict__ ctrls,
+                                                         GridDesc G0, const GridDesc* __restrict__ grids,
+                                                         const int2* __restrict__ cblocks, Scheme S, int step) {
+  const CellCtx C = cell_ctx(G0, grids, cblocks);
+  Ctrl* ctrl = ctrls + C.gi;
+  if (ctrl->fail_at <= step) return;
+  const GridDesc& G = C.G;
+  double s = 0.0;
+  int bad = 0;
+  if (C.live) {
+    const size_t N = (size_t)G.nx * G.ny, o = C.o;
+    const int i = (int)(o % G.nx), j = (int)(o / G.nx);
+    const real* FX = FXall + G.fx_off;
+    const real* FY = FYall + G.fy_off;
+    const real* W = Wall + G.w_off;
+    const real* W2 = W2all + G.w_off;
+    const real dt = real(ctrl->dt);
+    real L[4], w[4];
+    face_sum(FX, FY, G, i, j, 0, L);
+    const real a = real(1.0 / 3.0), b = real(2.0 / 3.0), q = real(2.0 / 3.0) * dt;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = (a * W[c * N + o] + b * W2[c * N + o]) + q * L[c];
+    bad = finish_cell(w, Wall + G.w_off, Aall, FX, FY, G, S, o, i, j, s);
   }
   block_reduce_commit(s, bad, ctrl, (step + 1) & 1, step + 1);
 }
@@ -615,7 +685,10 @@ static void launch_faces_out(const FaceLaunch& L, const real* W, const real* A, 
 
 template <class real>
 static void launch_faces(const FaceLaunch& L, const real* W, const real* A, real* FX, real* FY, hipStream_t st) {
-  if (L.out == (OUT_F | OUT_FT)) launch_faces_out<real, OUT_F | OUT_FT>(L, W, A, FX, FY, st);
+  // fluxes without time derivatives: the SSP-RK3 stages, which run with the LF flux only
+  if (L.out == OUT_F) launch_faces_shape<real, DFW_FLUX_LF, OUT_F>(L, W, A, FX, FY, st);
+  else if (L.out == (OUT_F | OUT_DF)) launch_faces_shape<real, DFW_FLUX_LF, OUT_F | OUT_DF>(L, W, A, FX, FY, st);
+  else if (L.out == (OUT_F | OUT_FT)) launch_faces_out<real, OUT_F | OUT_FT>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_FT | OUT_DF)) launch_faces_out<real, OUT_FT | OUT_DF>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_F | OUT_FT | OUT_OMEGA)) launch_faces_out<real, OUT_F | OUT_FT | OUT_OMEGA>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_FT | OUT_DF | OUT_OMEGA))
@@ -666,6 +739,10 @@ static dfw_status check_params(const dfw_params* p, int32_t dtype) {
   if (!(p->c1 >= 0) || !(p->c2 >= 0)) return fail(DFW_EINVAL, "c1, c2 must be >= 0");
   if (p->tile < 0 || p->tile >= kNumShapes) return fail(DFW_EINVAL, "tile must be in [0, dfw_num_tiles())");
   if (p->time_limiter != 0 && p->time_limiter != 1) return fail(DFW_EINVAL, "time_limiter must be 0 or 1");
+  if (p->time_scheme != DFW_TIME_S2O4 && p->time_scheme != DFW_TIME_SSPRK3)
+    return fail(DFW_EINVAL, "time_scheme must be DFW_TIME_S2O4 or DFW_TIME_SSPRK3");
+  if (p->time_scheme == DFW_TIME_SSPRK3 && (p->flux != DFW_FLUX_LF || p->time_limiter))
+    return fail(DFW_EINVAL, "SSP-RK3 runs with the LF flux and without the time limiter");
   if (dtype != DFW_F64 && dtype != DFW_F32) return fail(DFW_EDTYPE, "dtype must be DFW_F64 or DFW_F32");
   return DFW_OK;
 }
@@ -690,6 +767,7 @@ static Scheme make_scheme(const dfw_params* p) {
   S.d[1] = (1.0 - p->d_h) * p->d_l;
   S.d[2] = S.d[0];
   S.tl = p->time_limiter;
+  S.ts = p->time_scheme;
   return S;
 }
 
@@ -715,7 +793,7 @@ static GridDesc make_desc(const dfw_grid* g) {
 
 static unsigned cell_blocks(const GridDesc& G) { return (unsigned)(((size_t)G.nx * G.ny + kCellBlock - 1) / kCellBlock); }
 
-// The kernels of nsteps S2O4 steps on `st` (no synchronisation).  Single grid: grids/tiles/cblocks
+// The kernels of nsteps time steps (S2O4, or SSP-RK3) on `st` (no synchronisation).  Single grid: grids/tiles/cblocks
 // are null and G0 describes the grid; batch: the tables describe every grid.
 struct NoHook {
   void operator()(int) const {}
@@ -744,6 +822,34 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
   timed(DFW_K_SPEED, st, [&] {
     hipLaunchKernelGGL(k_speed<real>, dim3(nb), dim3(kCellBlock), 0, st, W, ctrls, G0, grids, cblocks, S, 0);
   });
+  if (S.ts == DFW_TIME_SSPRK3) {
+    for (int n = 0; n < nsteps; ++n) {
+      before_step(n);
+      L.step = n;
+      L.out = OUT_F;
+      L.lead = 1;
+      L.dt_hist = dt_hist;
+      timed(DFW_K_RK_FACES, st, [&] { launch_faces<real>(L, W, A, FX, FY, st); });
+      timed(DFW_K_RK_UPDATE, st, [&] {
+        hipLaunchKernelGGL((k_rk_stage<real, 1>), dim3(nb), dim3(kCellBlock), 0, st, W, (const real*)nullptr, FX, FY,
+                           Ws, ctrls, G0, grids, cblocks, n);
+      });
+      L.lead = 0;
+      L.dt_hist = nullptr;
+      timed(DFW_K_RK_FACES, st, [&] { launch_faces<real>(L, Ws, A, FX, FY, st); });
+      timed(DFW_K_RK_UPDATE, st, [&] {
+        hipLaunchKernelGGL((k_rk_stage<real, 2>), dim3(nb), dim3(kCellBlock), 0, st, W, Ws, FX, FY, R, ctrls, G0,
+                           grids, cblocks, n);
+      });
+      L.out = OUT_F | OUT_DF;
+      timed(DFW_K_RK_FACES, st, [&] { launch_faces<real>(L, R, A, FX, FY, st); });
+      timed(DFW_K_RK_UPDATE, st, [&] {
+        hipLaunchKernelGGL(k_rk_final<real>, dim3(nb), dim3(kCellBlock), 0, st, W, A, R, FX, FY, ctrls, G0, grids,
+                           cblocks, S, n);
+      });
+    }
+    return;
+  }
   for (int n = 0; n < nsteps; ++n) {
     before_step(n);
     L.step = n;
@@ -1173,6 +1279,7 @@ dfw_status dfw_adjoint(const dfw_grid* grid, const dfw_params* params, int32_t d
   if (s != DFW_OK) return s;
   if (dtype != DFW_F64) return fail(DFW_EDTYPE, "the adjoint is implemented in FP64 only");
   if (params->time_limiter) return fail(DFW_EINVAL, "the adjoint does not cover the time limiter");
+  if (params->time_scheme != DFW_TIME_S2O4) return fail(DFW_EINVAL, "the adjoint covers the S2O4 step only");
   if (!gW_final || !gW0) return fail(DFW_EINVAL, "gW_final and gW0 must be non-null");
   if (!dt_hist_dev && nsteps > 0) return fail(DFW_EINVAL, "dt_hist_dev is required");
   if ((s = check_ckpt(grid, dtype, nsteps, ckpt_every, ckpt, ckpt_bytes)) != DFW_OK) return s;

@@ -155,9 +155,10 @@ def test_max_speed_and_nonphysical():
     assert fs == 0
 
 
-def test_bitwise_determinism_and_transpose():
+@pytest.mark.parametrize("flux", [0, 1])
+def test_bitwise_determinism_and_transpose(flux):
     pr = WL.riemann4(36, 36, seed=21)
-    st = stepper(pr, gpu_params(1, cfl=0.4))
+    st = stepper(pr, gpu_params(flux, cfl=0.4))
     outs = []
     for _ in range(2):
         W = to_dev(pr.W)
