@@ -119,6 +119,8 @@ struct Params {
   int32_t flux;
   int32_t time_limiter; /* 1: eqs. (27)-(29) for the second-stage update */
   int32_t time_scheme;  /* 0: S2O4, eq. (21); 1: SSP-RK3, eq. (32) */
+  double t_end;         /* > 0: stop at this time (the last step is shortened to end on it) */
+  int32_t switch_rule;  /* 0: eq. (42) as printed (max of the three DF values); 1: their min (R31) */
 };
 
 /* ------------------------------------------------------------------------------------------ */
@@ -313,12 +315,13 @@ static T limiter_weight(const T* Q, const Params& prm) {
 }
 
 /* Section 3.3: the hybrid reconstruction of one cell.  a3 = (alpha_{i-1}, alpha_i, alpha_{i+1}).
- * If max(a3) < alpha_thres (strict, eq. (42)) the DF-weighted zero-mean quadratic
+ * If max(a3) < alpha_thres (strict, eq. (42); with switch_rule 1 the min of a3, reading R31:
+ * a discontinuity in any of the three cells) the DF-weighted zero-mean quadratic
  *   Q_i + alpha_i [ (Q_{i+1}-Q_i)/dx (x - x0) + (Q_{i-1}/2 - Q_i + Q_{i+1}/2)/dx^2 (x^2 - x1) ],
  * x0 = -dx/2, x1 = dx^2/3, replaces WENO-AO; otherwise WENO-AO.  Coefficients in xi. */
 template <class T>
 static void hybrid_poly(const T* Q, const T* a3, const Params& prm, T* P) {
-  T amax = mmax(mmax(a3[0], a3[1]), a3[2]);
+  T amax = prm.switch_rule == 1 ? mmin(mmin(a3[0], a3[1]), a3[2]) : mmax(mmax(a3[0], a3[1]), a3[2]);
   if (val(amax) < prm.alpha_thres) {
     const T& al = a3[1];
     T slope = Q[3] - Q[2];
@@ -1041,12 +1044,14 @@ struct dfo_grid {
 struct dfo_params {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux, time_limiter, time_scheme;
+  double t_end;
+  int32_t switch_rule;
 };
 
 static Grid to_grid(const dfo_grid* g) { return Grid{g->nx, g->ny, g->dx, g->dy, g->bc_x, g->bc_y}; }
 static Params to_params(const dfo_params* p) {
   return Params{p->gamma, p->cfl, p->dt_fixed, p->alpha_thres, p->d_h, p->d_l, p->eps_weno, p->c1, p->c2, p->flux,
-                p->time_limiter, p->time_scheme};
+                p->time_limiter, p->time_scheme, p->t_end, p->switch_rule};
 }
 
 /* 0 on success, 1 when the state holds a non-positive density/pressure or a non-finite value. */
@@ -1061,31 +1066,44 @@ void dfo_rhs(const double* W, const double* alpha, const dfo_grid* g, const dfo_
   spatial_operator(W, alpha, to_grid(g), to_params(p), dt, L, Lt, alpha_new);
 }
 
-/* nsteps S2O4 steps in place.  dt from the CFL condition unless dt_fixed > 0.  Returns 0, or 1
- * with *fail_step = the number of completed steps when a non-physical state is met. */
+/* nsteps time steps in place.  dt from the CFL condition unless dt_fixed > 0.  With t_end > 0 the
+ * run stops at t_end: the step that would pass it is shortened to t_end - t and ends exactly at
+ * t_end, and the remaining steps are skipped (dt_hist 0).  Returns 0, or 1 with *fail_step = the
+ * number of completed steps when a non-physical state is met. */
 int dfo_run(double* W, double* alpha, const dfo_grid* g, const dfo_params* p, int32_t nsteps,
             double* dt_hist, double* t_out, int32_t* fail_step) {
   Grid G = to_grid(g);
   Params P = to_params(p);
   double t = 0.0;
   if (fail_step) *fail_step = -1;
+  int done = 0; /* steps taken */
   for (int n = 0; n < nsteps; ++n) {
+    if (P.t_end > 0.0 && t >= P.t_end) {
+      if (dt_hist) dt_hist[n] = 0.0;
+      continue;
+    }
     double smax;
     bool ok = max_speed(W, G, P.gamma, &smax);
     if (!ok) {
-      if (fail_step) *fail_step = n;
+      if (fail_step) *fail_step = done;
       if (t_out) *t_out = t;
       return 1;
     }
     double dt = P.dt_fixed > 0.0 ? P.dt_fixed : P.cfl / smax;
+    bool last = false;
+    if (P.t_end > 0.0 && dt >= P.t_end - t) {
+      dt = P.t_end - t;
+      last = true;
+    }
     time_step(W, alpha, G, P, dt);
     if (dt_hist) dt_hist[n] = dt;
-    t += dt;
+    t = last ? P.t_end : t + dt;
+    ++done;
   }
   {
     double smax;
     if (!max_speed(W, G, P.gamma, &smax)) {
-      if (fail_step) *fail_step = nsteps;
+      if (fail_step) *fail_step = done;
       if (t_out) *t_out = t;
       return 1;
     }

@@ -128,6 +128,22 @@ def test_hybrid_branch_special_cases():
     np.testing.assert_allclose(O.hybrid(Q, [0.5, 0.1, 0.1], prm), O.weno_ao(Q, prm), atol=0)
 
 
+def test_hybrid_switch_rule_min():
+    """Reading R31 (switch_rule 1): the DF quadratic is taken when any of the three cells is below the
+    threshold; with every value below it, or every value above it, the two rules agree."""
+    rng = np.random.default_rng(4)
+    Q = rng.normal(size=5)
+    p0, p1 = O.make_params(alpha_thres=0.5), O.make_params(alpha_thres=0.5, switch_rule=1)
+    wa = O.weno_ao(Q, p0)
+    np.testing.assert_allclose(O.hybrid(Q, [1.0, 0.3, 1.0], p0), wa, atol=0)        # max rule: WENO-AO
+    Pm = O.hybrid(Q, [1.0, 0.3, 1.0], p1)                                           # min rule: p_DF, alpha_i = 0.3
+    np.testing.assert_allclose(Pm, O.hybrid(Q, [0.1, 0.3, 0.2], p0), atol=0)
+    np.testing.assert_allclose(O.hybrid(Q, [0.1, 1.0, 1.0], p1), O.candidate(1) @ Q, atol=1e-14)  # alpha_i = 1: p1
+    for a3 in ([0.1, 0.2, 0.3], [0.9, 0.6, 1.0]):
+        np.testing.assert_allclose(O.hybrid(Q, a3, p1), O.hybrid(Q, a3, p0), atol=0)
+    np.testing.assert_allclose(O.hybrid(Q, [0.5, 0.7, 0.5], p1), wa, atol=0)     # strict: min == threshold
+
+
 # ----------------------------------------------------------------------------------------------
 # Characteristic basis, fluxes
 # ----------------------------------------------------------------------------------------------
@@ -790,3 +806,23 @@ def test_ssprk3_conservation_symmetry_positivity():
     # the SSP-RK3 result differs from S2O4 on the same data
     Ws, _, _, _, _ = O.run(W0, pr.alpha, g, O.make_params(flux=O.FLUX_LF, cfl=0.4), 20)
     assert np.abs(Ws - W).max() > 1e-6
+
+
+def test_t_end_stops_exactly_and_matches_the_exact_solution():
+    """A run with t_end ends on t_end (the last step shortened), later steps are skipped with dt 0 and
+    change nothing, and the state there matches the exact advected density wave."""
+    pr = WL.density_wave(32)
+    g = O.make_grid(32, 32, pr.dx, pr.dy)
+    p = O.make_params(cfl=0.5, t_end=0.3)
+    W, a, t, dth, fs = O.run(pr.W, pr.alpha, g, p, 200)
+    assert fs == -1 and t == 0.3
+    k = int(np.count_nonzero(dth))
+    assert 0 < k < 200 and np.all(dth[k:] == 0.0) and np.all(dth[:k] > 0.0)
+    assert dth[k - 1] < dth[k - 2]
+    assert abs(dth.sum() - 0.3) <= 1e-15
+    W2, a2, t2, _, _ = O.run(pr.W, pr.alpha, g, p, k)
+    assert np.array_equal(W, W2) and np.array_equal(a, a2) and t2 == 0.3
+    err = np.abs(W[0] - WL.density_wave_avg(32, 32, t=0.3)).mean()
+    Wu, _, tu, _, _ = O.run(pr.W, pr.alpha, g, O.make_params(dt_fixed=0.3 / k), k)
+    err_u = np.abs(Wu[0] - WL.density_wave_avg(32, 32, t=tu)).mean()
+    assert 0.8 * err_u <= err <= 1.25 * err_u, (err, err_u)
