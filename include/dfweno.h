@@ -70,13 +70,18 @@ typedef struct {
  *                the time limiter, with it are rejected with DFW_EINVAL).  dt comes from the CFL
  *                condition on W^n, alpha^n drives the hybrid switch in all three stages and
  *                alpha^{n+1} is built from the third stage's Gauss points.  dfw_adjoint covers
- *                DFW_TIME_S2O4 only. */
+ *                DFW_TIME_S2O4 only.
+ *   t_end        > 0: the run stops at time t_end.  The step that would pass it is shortened to
+ *                end exactly on t_end (so the returned t equals t_end) and any remaining steps
+ *                are skipped and record dt = 0 in dt_hist; nsteps is then an upper bound on the
+ *                steps taken.  0: exactly nsteps steps [0].  Must be >= 0; dfw_adjoint requires 0. */
 typedef struct {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
   int32_t tile;
   int32_t time_limiter;
   int32_t time_scheme;
+  double t_end;
 } dfw_params;
 
 /* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */
@@ -86,7 +91,8 @@ size_t dfw_workspace_bytes(const dfw_grid* grid, int32_t dtype);
  * (eq. (32)) when params->time_scheme says so.
  *   W, alpha        device, in/out.
  *   dt_hist_dev     device, optional (may be NULL): receives the nsteps time increments (FP64).
- *   t_out           host, optional: sum of the time increments actually taken.
+ *   t_out           host, optional: the time reached (sum of the increments taken; t_end exactly
+ *                   when the run reached it).
  *   fail_step       host, optional: -1 on success; otherwise the number of completed steps when
  *                   a non-physical state was found (0 = the input).  W then holds that state and
  *                   later steps are skipped; the call returns DFW_ENONPHYS.

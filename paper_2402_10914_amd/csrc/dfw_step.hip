@@ -35,8 +35,8 @@ namespace dfw {
 // ------------------------------------------------------------------------------------------------
 struct Ctrl {
   unsigned long long smax_bits[2];  // running max signal speed / dx for the next step (ping-pong)
-  double dt;                        // dt of the current step
-  double t;                         // accumulated time
+  double dt;                        // dt of the current step; 0 when the step is skipped (t_end reached)
+  double t;                         // accumulated time (advanced by the last kernel of a step)
   int fail_at;                      // steps completed when a non-physical state was first met,
                                     // kNoFail if none; kernels of step n skip once fail_at <= n
   int pad[3];
@@ -59,6 +59,7 @@ struct Scheme {
   double d[4];
   int tl;  // non-linear time limiter (eqs. (27)-(29)) on
   int ts;  // time scheme: DFW_TIME_S2O4 (eq. (21)) or DFW_TIME_SSPRK3 (eq. (32))
+  double t_end;  // > 0: stop at this time
 };
 
 // OUT_OMEGA: time-limiter weight of each interface: with OUT_F (first stage) stored in plane 9, without
@@ -158,17 +159,25 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
 
-  // ---- dt of this step
+  // ---- dt of this step.  The first launch of a step computes it (every tile the same value: t and
+  // the speed slot do not change during this launch) and records it; later launches read it.  With
+  // t_end > 0 the step that would pass t_end ends on it, and later steps are skipped (dt = 0).
   double dtd;
-  if (dt_host > 0.0) dtd = dt_host;
-  else if (lead) dtd = S.cfl / __longlong_as_double((long long)ctrl->smax_bits[step & 1]);
-  else dtd = ctrl->dt;
+  if (lead) {
+    dtd = dt_host > 0.0 ? dt_host : S.cfl / __longlong_as_double((long long)ctrl->smax_bits[step & 1]);
+    if (S.t_end > 0.0) {
+      const double rem = S.t_end - ctrl->t;
+      if (dtd >= rem) dtd = rem > 0.0 ? rem : 0.0;
+    }
+  } else {
+    dtd = dt_host > 0.0 ? dt_host : ctrl->dt;
+  }
   if (lead && lead_tile && tid == 0) {
     ctrl->dt = dtd;
-    ctrl->t += dtd;
-    ctrl->smax_bits[(step + 1) & 1] = 0ull;
+    if (dtd > 0.0) ctrl->smax_bits[(step + 1) & 1] = 0ull;
     if (dt_hist) dt_hist[(size_t)gi * nsteps + step] = dtd;
   }
+  if (!(dtd > 0.0)) return;  // uniform over the launch
   const real dt = real(dtd);
   const Coef<real> k = make_coef<real>(S);
 
@@ -357,7 +366,7 @@ __global__ __launch_bounds__(kCellBlock) void k_update1(const real* __restrict__
                                                         const int2* __restrict__ cblocks, int step, int tl) {
   const CellCtx C = cell_ctx(G0, grids, cblocks);
   Ctrl* ctrl = ctrls + C.gi;
-  if (ctrl->fail_at <= step || !C.live) return;
+  if (ctrl->fail_at <= step || !(ctrl->dt > 0.0) || !C.live) return;
   const GridDesc& G = C.G;
   const size_t N = (size_t)G.nx * G.ny, o = C.o;
   const int i = (int)(o % G.nx), j = (int)(o / G.nx);
@@ -447,6 +456,13 @@ __device__ __forceinline__ int finish_cell(const real* w, real* W, real* Aall, c
   return cell_speed(w, S, G, s) ? 0 : 1;
 }
 
+// The last kernel of a step advances the grid's time, from the thread of its cell 0 (no other
+// thread of the launch reads t); the step that reaches t_end ends exactly on it.
+__device__ __forceinline__ void advance_time(Ctrl* ctrl, const Scheme& S, double dtd) {
+  const double t = ctrl->t;
+  ctrl->t = (S.t_end > 0.0 && dtd >= S.t_end - t) ? S.t_end : t + dtd;
+}
+
 template <class real>
 __global__ __launch_bounds__(kCellBlock) void k_update2(real* __restrict__ Wall, real* __restrict__ Aall,
                                                         const real* __restrict__ Rall, const real* __restrict__ FXall,
@@ -455,7 +471,8 @@ __global__ __launch_bounds__(kCellBlock) void k_update2(real* __restrict__ Wall,
                                                         const int2* __restrict__ cblocks, Scheme S, int step) {
   const CellCtx C = cell_ctx(G0, grids, cblocks);
   Ctrl* ctrl = ctrls + C.gi;
-  if (ctrl->fail_at <= step) return;  // uniform over the workgroup: one grid per workgroup
+  const double dtd = ctrl->dt;
+  if (ctrl->fail_at <= step || !(dtd > 0.0)) return;  // uniform over the workgroup: one grid per workgroup
   const GridDesc& G = C.G;
   double s = 0.0;
   int bad = 0;
@@ -465,7 +482,8 @@ __global__ __launch_bounds__(kCellBlock) void k_update2(real* __restrict__ Wall,
     const real* FX = FXall + G.fx_off;
     const real* FY = FYall + G.fy_off;
     const real* R = Rall + G.w_off;
-    const real dt = real(ctrl->dt);
+    const real dt = real(dtd);
+    if (o == 0) advance_time(ctrl, S, dtd);
     real Lt[4], w[4];
     face_sum(FX, FY, G, i, j, 4, Lt);
     const real r3 = dt * dt * real(1.0 / 3.0);
@@ -486,7 +504,7 @@ __global__ __launch_bounds__(kCellBlock) void k_rk_stage(const real* __restrict_
                                                          const int2* __restrict__ cblocks, int step) {
   const CellCtx C = cell_ctx(G0, grids, cblocks);
   Ctrl* ctrl = ctrls + C.gi;
-  if (ctrl->fail_at <= step || !C.live) return;
+  if (ctrl->fail_at <= step || !(ctrl->dt > 0.0) || !C.live) return;
   const GridDesc& G = C.G;
   const size_t N = (size_t)G.nx * G.ny, o = C.o;
   const int i = (int)(o % G.nx), j = (int)(o / G.nx);
@@ -516,7 +534,8 @@ __global__ __launch_bounds__(kCellBlock) void k_rk_final(real* __restrict__ Wall
                                                          const int2* __restrict__ cblocks, Scheme S, int step) {
   const CellCtx C = cell_ctx(G0, grids, cblocks);
   Ctrl* ctrl = ctrls + C.gi;
-  if (ctrl->fail_at <= step) return;
+  const double dtd = ctrl->dt;
+  if (ctrl->fail_at <= step || !(dtd > 0.0)) return;
   const GridDesc& G = C.G;
   double s = 0.0;
   int bad = 0;
@@ -527,7 +546,8 @@ __global__ __launch_bounds__(kCellBlock) void k_rk_final(real* __restrict__ Wall
     const real* FY = FYall + G.fy_off;
     const real* W = Wall + G.w_off;
     const real* W2 = W2all + G.w_off;
-    const real dt = real(ctrl->dt);
+    const real dt = real(dtd);
+    if (o == 0) advance_time(ctrl, S, dtd);
     real L[4], w[4];
     face_sum(FX, FY, G, i, j, 0, L);
     const real a = real(1.0 / 3.0), b = real(2.0 / 3.0), q = real(2.0 / 3.0) * dt;
@@ -743,6 +763,7 @@ static dfw_status check_params(const dfw_params* p, int32_t dtype) {
     return fail(DFW_EINVAL, "time_scheme must be DFW_TIME_S2O4 or DFW_TIME_SSPRK3");
   if (p->time_scheme == DFW_TIME_SSPRK3 && (p->flux != DFW_FLUX_LF || p->time_limiter))
     return fail(DFW_EINVAL, "SSP-RK3 runs with the LF flux and without the time limiter");
+  if (!(p->t_end >= 0.0)) return fail(DFW_EINVAL, "t_end must be >= 0 (0: no end time)");
   if (dtype != DFW_F64 && dtype != DFW_F32) return fail(DFW_EDTYPE, "dtype must be DFW_F64 or DFW_F32");
   return DFW_OK;
 }
@@ -768,6 +789,7 @@ static Scheme make_scheme(const dfw_params* p) {
   S.d[2] = S.d[0];
   S.tl = p->time_limiter;
   S.ts = p->time_scheme;
+  S.t_end = p->t_end;
   return S;
 }
 
@@ -815,7 +837,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
   L.G0 = G0;
   L.ctrls = ctrls;
   L.S = S;
-  L.dt_host = p->dt_fixed > 0 ? p->dt_fixed : 0.0;
+  const double dt_first = p->dt_fixed > 0 ? p->dt_fixed : 0.0;  // later launches of a step read ctrl->dt
   L.nsteps = nsteps;
   const unsigned nb = (unsigned)ncblocks;
   hipLaunchKernelGGL(k_ctrl_init, dim3((nctrl + 63) / 64), dim3(64), 0, st, ctrls, nctrl);
@@ -828,6 +850,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
       L.step = n;
       L.out = OUT_F;
       L.lead = 1;
+      L.dt_host = dt_first;
       L.dt_hist = dt_hist;
       timed(DFW_K_RK_FACES, st, [&] { launch_faces<real>(L, W, A, FX, FY, st); });
       timed(DFW_K_RK_UPDATE, st, [&] {
@@ -835,6 +858,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
                            Ws, ctrls, G0, grids, cblocks, n);
       });
       L.lead = 0;
+      L.dt_host = 0.0;
       L.dt_hist = nullptr;
       timed(DFW_K_RK_FACES, st, [&] { launch_faces<real>(L, Ws, A, FX, FY, st); });
       timed(DFW_K_RK_UPDATE, st, [&] {
@@ -855,6 +879,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
     L.step = n;
     L.out = OUT_F | OUT_FT | (S.tl ? OUT_OMEGA : 0);
     L.lead = 1;
+    L.dt_host = dt_first;
     L.dt_hist = dt_hist;
     timed(DFW_K_FACES1, st, [&] { launch_faces<real>(L, W, A, FX, FY, st); });
     timed(DFW_K_UPDATE1, st, [&] {
@@ -863,6 +888,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
     });
     L.out = OUT_FT | OUT_DF | (S.tl ? OUT_OMEGA : 0);
     L.lead = 0;
+    L.dt_host = 0.0;
     L.dt_hist = nullptr;
     timed(DFW_K_FACES2, st, [&] { launch_faces<real>(L, Ws, A, FX, FY, st); });
     timed(DFW_K_UPDATE2, st, [&] {
@@ -1280,6 +1306,7 @@ dfw_status dfw_adjoint(const dfw_grid* grid, const dfw_params* params, int32_t d
   if (dtype != DFW_F64) return fail(DFW_EDTYPE, "the adjoint is implemented in FP64 only");
   if (params->time_limiter) return fail(DFW_EINVAL, "the adjoint does not cover the time limiter");
   if (params->time_scheme != DFW_TIME_S2O4) return fail(DFW_EINVAL, "the adjoint covers the S2O4 step only");
+  if (params->t_end > 0.0) return fail(DFW_EINVAL, "the adjoint takes its time steps from dt_hist; t_end must be 0");
   if (!gW_final || !gW0) return fail(DFW_EINVAL, "gW_final and gW0 must be non-null");
   if (!dt_hist_dev && nsteps > 0) return fail(DFW_EINVAL, "dt_hist_dev is required");
   if ((s = check_ckpt(grid, dtype, nsteps, ckpt_every, ckpt, ckpt_bytes)) != DFW_OK) return s;

@@ -1,0 +1,134 @@
+"""Robustness sweeps of Section 4.3 (Tables 5-7): the largest reference Mach number at which a
+scheme runs a problem to its end without meeting a non-physical state (rho <= 0, p <= 0 or a
+non-finite value), found by a bisection in which every round advances a set of candidate Mach
+numbers together as one batch of independent grids (one captured hipGraph launch).
+
+Schemes, the paper's two solvers: ``gks`` = S2O4 with the gas-kinetic flux and the non-linear
+time limiter (eqs. (21), (27)-(29)); ``lf`` = SSP-RK3 with the Lax-Friedrichs flux (eq. (32)).
+Reconstructions: ``hybrid`` (DF threshold 0.5, eq. (42)) and ``weno_ao`` (threshold 0: the switch
+never engages and every interface uses WENO-AO).  CFL 0.5, as the paper uses for these problems.
+
+    python -m paper_2402_10914_amd.robustness --problems 123,hurricane,rarefaction
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import workloads as WL
+
+SOLVERS = ("gks", "lf")
+RECONS = ("weno_ao", "hybrid")
+
+
+def solver_params(solver: str, recon: str, t_end: float = 0.0):
+    from .api import FLUX_GKS, FLUX_LF, TIME_S2O4, TIME_SSPRK3, Params
+    thres = {"hybrid": 0.5, "weno_ao": 0.0}[recon]
+    if solver == "gks":
+        return Params(flux=FLUX_GKS, cfl=0.5, alpha_thres=thres, time_limiter=1, time_scheme=TIME_S2O4, t_end=t_end)
+    if solver == "lf":
+        return Params(flux=FLUX_LF, cfl=0.5, alpha_thres=thres, time_scheme=TIME_SSPRK3, t_end=t_end)
+    raise ValueError(f"unknown solver {solver!r}")
+
+
+def _max_signal_speed(pr) -> float:
+    W = pr.W
+    rho = W[0]
+    u, v = W[1] / rho, W[2] / rho
+    p = (pr.gamma - 1.0) * (W[3] - 0.5 * rho * (u * u + v * v))
+    c = np.sqrt(pr.gamma * p / rho)
+    return float(max(((np.abs(u) + c) / pr.dx).max(), ((np.abs(v) + c) / pr.dy).max()))
+
+
+def step_cap(pr) -> int:
+    """Upper bound on the steps to the problem's end: four times the steps the initial signal
+    speed would need (the speeds of these flows grow by well under that factor)."""
+    t_end = pr.extra.get("t_end", 0.0)
+    if t_end <= 0.0:
+        return pr.nsteps
+    dt0 = pr.cfl / _max_signal_speed(pr)
+    return int(math.ceil(4.0 * t_end / dt0)) + 20
+
+
+def survives(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None):
+    """Runs the problem at every Mach number of `machs` as one batch; returns [bool] (survived)."""
+    import torch
+    from .api import Batch
+    dtype = torch.float64 if dtype is None else dtype
+    make = WL.ROBUSTNESS[problem]
+    probs = [make(float(m)) if n is None else make(float(m), n=n) for m in machs]
+    t_end = probs[0].extra.get("t_end", 0.0)
+    params = solver_params(solver, recon, t_end)
+    b = Batch([(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y) for p in probs], params, dtype, 0)
+    W, A = b.pack([p.W for p in probs], [p.alpha for p in probs])
+    nsteps = max(step_cap(p) for p in probs)
+    t, fs = b.run(W, A, nsteps, use_graph=True)
+    out = []
+    for ti, f in zip(t, fs):
+        if f != -1:
+            out.append(False)
+        elif t_end > 0.0 and ti != t_end:
+            raise RuntimeError(f"{problem}: t_end not reached in {nsteps} steps (t = {ti})")
+        else:
+            out.append(True)
+    return out
+
+
+def max_mach(problem: str, solver: str, recon: str, lo: float = 1.0, hi: float = 200.0, k: int = 16,
+             rtol: float = 0.01, runner=None, **kw) -> dict:
+    """Bisection for the survival boundary in [lo, hi]: each round evaluates k Mach numbers spaced
+    geometrically strictly inside the bracket; the bracket becomes (largest survivor below the first
+    failure, first failure).  Stops when hi / lo <= 1 + rtol.  `runner(machs) -> [bool]` defaults to
+    the GPU batch (`survives`).  Returns {"max_mach": lo, "first_fail": hi, ...}; max_mach is None
+    when lo already fails and first_fail None when hi survives."""
+    run = runner or (lambda ms: survives(problem, ms, solver, recon, **kw))
+    evals, rounds = 2, 0
+    ok_lo, ok_hi = run([lo, hi])
+    res = dict(problem=problem, solver=solver, recon=recon, rtol=rtol, k=k)
+    if not ok_lo:
+        return dict(res, max_mach=None, first_fail=lo, rounds=0, evaluations=evals)
+    if ok_hi:
+        return dict(res, max_mach=hi, first_fail=None, rounds=0, evaluations=evals)
+    while hi / lo > 1.0 + rtol:
+        pts = np.geomspace(lo, hi, k + 2)[1:-1]
+        ok = run([float(p) for p in pts])
+        evals += len(pts)
+        rounds += 1
+        fails = [i for i, o in enumerate(ok) if not o]
+        if not fails:
+            lo = float(pts[-1])
+        else:
+            j = fails[0]
+            hi = float(pts[j])
+            if j > 0:
+                lo = float(pts[j - 1])
+    return dict(res, max_mach=lo, first_fail=hi, rounds=rounds, evaluations=evals)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--problems", default="123,hurricane,rarefaction")
+    ap.add_argument("--solvers", default="gks,lf")
+    ap.add_argument("--recons", default="weno_ao,hybrid")
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--rtol", type=float, default=0.01)
+    ap.add_argument("--lo", type=float, default=1.0)
+    ap.add_argument("--hi", type=float, default=200.0)
+    a = ap.parse_args(argv)
+    for prob in a.problems.split(","):
+        for solver in a.solvers.split(","):
+            for recon in a.recons.split(","):
+                t0 = time.time()
+                r = max_mach(prob, solver, recon, lo=a.lo, hi=a.hi, k=a.k, rtol=a.rtol)
+                r["seconds"] = round(time.time() - t0, 2)
+                print(json.dumps(r), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -21,6 +21,9 @@ Workloads (the paper's test problems are analytic, so no dataset is involved):
                        to 10 and pressure ratios up to 1e3.
   * ``batch``          ragged set of independent grids (half density wave, half Riemann).
   * ``bumps``          density wave plus seeded Gaussian bumps (adjoint workload) and its target.
+  * ``problem_123``, ``hurricane``, ``rarefaction2d``
+                       the robustness problems of Section 4.3, each parameterised by its reference
+                       Mach number (Tables 5-7 report the largest Mach number a scheme survives).
 """
 from __future__ import annotations
 
@@ -248,3 +251,68 @@ def bumps_target(n, t, seed=1025, nbumps=16, amp=0.01, width=0.05) -> np.ndarray
     xc = _centres(n, 0.0, d)[None, :]
     yc = _centres(n, 0.0, d)[:, None]
     return 1.0 + 0.2 * np.sin(np.pi * (xc + yc - 2.0 * t)) + _bump_field(n, rng, nbumps, amp, width)
+
+
+# ------------------------------------------------------------------------------------------------
+# Robustness problems of Section 4.3 (deterministic; the Mach number is the parameter).
+# ------------------------------------------------------------------------------------------------
+
+def problem_123(mach, n=100, gamma=GAMMA) -> Problem:
+    """The 123 problem: (rho, u, p) = (1, -2, p0) on [0, 0.5) and (1, 2, p0) on [0.5, 1], two strong
+    rarefactions leaving near-vacuum between them.  The reference Mach number |u| / sqrt(gamma p0 /
+    rho) fixes p0 = rho u^2 / (gamma Ma^2).  n cells (ny = 1, dy = dx), free (transmissive)
+    boundaries, final time 0.14."""
+    d = 1.0 / n
+    xc = _centres(n, 0.0, d)[None, :]
+    rho = np.ones((1, n))
+    u = np.where(xc < 0.5, -2.0, 2.0)
+    p0 = 1.0 * 2.0 ** 2 / (gamma * mach ** 2)
+    W = _assemble(rho, u, 0.0 * u, p0 * rho, gamma)
+    return Problem("problem_123", n, 1, 0.0, 0.0, d, d, BC_TRANSMISSIVE, BC_TRANSMISSIVE, W, np.ones((1, n)),
+                   cfl=0.5, gamma=gamma, extra={"mach": float(mach), "p0": p0, "t_end": 0.14})
+
+
+def hurricane(mach, n=400, gamma=GAMMA, rho0=1.0, A=25.0) -> Problem:
+    """Hurricane-like flow: (rho, u, v, p) = (rho0, v0 sin(theta), -v0 cos(theta), A rho0^gamma) on
+    [-2,2]^2, theta the polar angle of (x, y), so the velocity is a rotation of speed |v0| about the
+    origin (the paper writes theta = arctan(y/x); read as the polar angle).  Reference Mach number
+    |v0| / c0 with c0 = sqrt(gamma A rho0^(gamma-1)).  Point values at the cell centres; dx = 4 / n
+    (n = 400 gives the paper's 1/100), transmissive ("non-reflecting") boundaries; the test is
+    survival over the first 50 steps."""
+    d = 4.0 / n
+    xc = _centres(n, -2.0, d)[None, :]
+    yc = _centres(n, -2.0, d)[:, None]
+    r = np.sqrt(xc * xc + yc * yc)
+    c0 = math.sqrt(gamma * A * rho0 ** (gamma - 1.0))
+    v0 = mach * c0
+    rho = np.full((n, n), rho0)
+    u = v0 * (yc / r) + 0.0 * xc   # v0 sin(theta)
+    v = -v0 * (xc / r) + 0.0 * yc  # -v0 cos(theta)
+    W = _assemble(rho, u, v, A * rho0 ** gamma * np.ones((n, n)), gamma)
+    return Problem("hurricane", n, n, -2.0, -2.0, d, d, BC_TRANSMISSIVE, BC_TRANSMISSIVE, W, np.ones((n, n)),
+                   cfl=0.5, nsteps=50, gamma=gamma, extra={"mach": float(mach), "v0": v0, "c0": c0})
+
+
+def rarefaction2d(mach, n=400, gamma=GAMMA, A=1.5, q=0.6323) -> Problem:
+    """Interaction of planar rarefaction waves on [0,1]^2 split at (0.5, 0.5):
+    SW (1, -q, -q, 1.5), SE (rho, q, -q, A rho^gamma), NE (1, q, q, 1.5), NW (rho, -q, q, A rho^gamma)
+    with q = 0.6323 and A = 1.5 (the NE state is garbled in the paper; read as (1, q, q, 1.5)).
+    The reference Mach number sqrt(U^2 + V^2) / sqrt(gamma A rho^(gamma-1)) of the SE and NW states
+    fixes rho = ((U^2 + V^2) / (gamma A Ma^2))^(1 / (gamma - 1)).  dx = 1 / n (n = 400 in the
+    paper), free boundaries, final time 0.15."""
+    d = 1.0 / n
+    xc = _centres(n, 0.0, d)[None, :] + 0.0 * _centres(n, 0.0, d)[:, None]
+    yc = _centres(n, 0.0, d)[:, None] + 0.0 * _centres(n, 0.0, d)[None, :]
+    rho_q = ((2.0 * q * q) / (gamma * A * mach ** 2)) ** (1.0 / (gamma - 1.0))
+    east, north = xc >= 0.5, yc >= 0.5
+    diag = east == north  # SW and NE
+    rho = np.where(diag, 1.0, rho_q)
+    u = np.where(east, q, -q)
+    v = np.where(north, q, -q)
+    p = np.where(diag, 1.5, A * rho_q ** gamma)
+    W = _assemble(rho, u, v, p, gamma)
+    return Problem("rarefaction2d", n, n, 0.0, 0.0, d, d, BC_TRANSMISSIVE, BC_TRANSMISSIVE, W, np.ones((n, n)),
+                   cfl=0.5, gamma=gamma, extra={"mach": float(mach), "rho": rho_q, "t_end": 0.15})
+
+
+ROBUSTNESS = {"123": problem_123, "hurricane": hurricane, "rarefaction": rarefaction2d}
