@@ -74,7 +74,11 @@ typedef struct {
  *   t_end        > 0: the run stops at time t_end.  The step that would pass it is shortened to
  *                end exactly on t_end (so the returned t equals t_end) and any remaining steps
  *                are skipped and record dt = 0 in dt_hist; nsteps is then an upper bound on the
- *                steps taken.  0: exactly nsteps steps [0].  Must be >= 0; dfw_adjoint requires 0. */
+ *                steps taken.  0: exactly nsteps steps [0].  Must be >= 0; dfw_adjoint requires 0.
+ *   switch_rule  0: the hybrid switch of eq. (42) as printed, DF quadratic when the largest DF
+ *                value of the cell and its two neighbours is below alpha_thres [0]; 1: when the
+ *                smallest is (a discontinuity in any of the three cells).  Option for ablations
+ *                and the robustness sweeps; the adjoint follows the same rule. */
 typedef struct {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
@@ -82,6 +86,7 @@ typedef struct {
   int32_t time_limiter;
   int32_t time_scheme;
   double t_end;
+  int32_t switch_rule;
 } dfw_params;
 
 /* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */

@@ -32,7 +32,8 @@ class dfw_params(ctypes.Structure):
                 ("alpha_thres", ctypes.c_double), ("d_h", ctypes.c_double), ("d_l", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("flux", ctypes.c_int32), ("tile", ctypes.c_int32), ("time_limiter", ctypes.c_int32),
-                ("time_scheme", ctypes.c_int32), ("t_end", ctypes.c_double)]
+                ("time_scheme", ctypes.c_int32), ("t_end", ctypes.c_double),
+                ("switch_rule", ctypes.c_int32)]
 
 
 class DFWError(RuntimeError):

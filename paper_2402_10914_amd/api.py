@@ -39,12 +39,13 @@ class Params:
     time_limiter: int = 0  # 1: non-linear time limiter of Section 2.2, eqs. (27)-(29)
     time_scheme: int = TIME_S2O4  # TIME_SSPRK3: eq. (32) of Section 2.3 (LF flux only)
     t_end: float = 0.0  # > 0: stop at this time (the last step is shortened; nsteps is an upper bound)
+    switch_rule: int = 0  # 1: hybrid switch on the min of the three DF values (eq. (42) prints the max)
 
     def struct(self) -> _lib.dfw_params:
         return _lib.dfw_params(float(self.gamma), float(self.cfl), float(self.dt_fixed), float(self.alpha_thres),
                                float(self.d_h), float(self.d_l), float(self.eps_weno), float(self.c1),
                                float(self.c2), int(self.flux), int(self.tile), int(self.time_limiter),
-                               int(self.time_scheme), float(self.t_end))
+                               int(self.time_scheme), float(self.t_end), int(self.switch_rule))
 
 
 def tile_shapes():

@@ -219,10 +219,8 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
   real p1_2 = real(0.5) * (Q1 + Q3) - Q2;
   real lP0 = lP[0], lP1 = NDEG > 1 ? lP[1] : real(0), lP2 = NDEG > 2 ? lP[2] : real(0);
   real lP3 = NDEG > 3 ? lP[3] : real(0), lP4 = NDEG > 4 ? lP[4] : real(0);
-  real amax = a_lo > a_c ? a_lo : a_c;
-  amax = amax > a_hi ? amax : a_hi;
   real l10, l11, l12;  // adjoints of p1's coefficients
-  if (amax < k.alpha_thres) {
+  if (df_switch(a_lo, a_c, a_hi, k)) {
     la_c += lP0 * (p1_0 - Q2) + lP1 * p1_1 + lP2 * p1_2;
     lQ[2] += lP0 * (real(1) - a_c);
     if (P) {

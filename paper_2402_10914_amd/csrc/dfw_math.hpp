@@ -21,7 +21,20 @@ struct Coef {
   real dr[3];     // d_k / d_3
   real inv_d3;
   real K2, k4K2;  // K + 2 and 4 / (K + 2)
+  int sw_min;     // hybrid switch on the min of the three DF values instead of the max
 };
+
+// Eq. (42): the DF quadratic replaces WENO-AO for a cell when the largest DF value of the cell and
+// its two neighbours along the sweep is below the threshold (strict).  sw_min takes the smallest
+// instead (a discontinuity in any of the three cells), a reading kept as an option.
+template <class real>
+DFW_HD inline bool df_switch(real a_lo, real a_c, real a_hi, const Coef<real>& k) {
+  real mx = a_lo > a_c ? a_lo : a_c;
+  mx = mx > a_hi ? mx : a_hi;
+  real mn = a_lo < a_c ? a_lo : a_c;
+  mn = mn < a_hi ? mn : a_hi;
+  return (k.sw_min ? mn : mx) < k.alpha_thres;
+}
 
 // ------------------------------------------------------------------------------------------------
 // Characteristic basis (eigenvectors of the normal flux Jacobian at the arithmetic mean of the two
@@ -120,9 +133,7 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   real p1_0 = (real(5) * Q2 + real(2) * Q3 - Q1) * real(1.0 / 6.0);
   real p1_1 = Q3 - Q2;
   real p1_2 = real(0.5) * (Q1 + Q3) - Q2;
-  real amax = a_lo > a_c ? a_lo : a_c;
-  amax = amax > a_hi ? amax : a_hi;
-  if (amax < k.alpha_thres) {
+  if (df_switch(a_lo, a_c, a_hi, k)) {
     P[0] = Q2 + a_c * (p1_0 - Q2);
     if (NDEG > 1) P[1] = a_c * p1_1;
     if (NDEG > 2) P[2] = a_c * p1_2;

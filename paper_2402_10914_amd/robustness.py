@@ -5,8 +5,11 @@ numbers together as one batch of independent grids (one captured hipGraph launch
 
 Schemes, the paper's two solvers: ``gks`` = S2O4 with the gas-kinetic flux and the non-linear
 time limiter (eqs. (21), (27)-(29)); ``lf`` = SSP-RK3 with the Lax-Friedrichs flux (eq. (32)).
-Reconstructions: ``hybrid`` (DF threshold 0.5, eq. (42)) and ``weno_ao`` (threshold 0: the switch
-never engages and every interface uses WENO-AO).  CFL 0.5, as the paper uses for these problems.
+Reconstructions: ``weno_ao`` (DF threshold 0: the switch never engages), ``hybrid`` (threshold 0.5,
+the switch of eq. (42) as printed: the largest DF value of the three cells below the threshold) and
+``hybrid_min`` (the same with the smallest of the three).  Initial DF: ``one`` (alpha^0 = 1) or
+``initial`` (the DF product of the initial state's own Gauss-point values, one evaluation of the
+operator before the first step).  CFL 0.5, as the paper uses for these problems.
 
     python -m paper_2402_10914_amd.robustness --problems 123,hurricane,rarefaction
 """
@@ -23,17 +26,32 @@ import numpy as np
 from . import workloads as WL
 
 SOLVERS = ("gks", "lf")
-RECONS = ("weno_ao", "hybrid")
+RECONS = ("weno_ao", "hybrid", "hybrid_min")
+ALPHA0 = ("one", "initial")
 
 
 def solver_params(solver: str, recon: str, t_end: float = 0.0):
     from .api import FLUX_GKS, FLUX_LF, TIME_S2O4, TIME_SSPRK3, Params
-    thres = {"hybrid": 0.5, "weno_ao": 0.0}[recon]
+    thres, rule = {"hybrid": (0.5, 0), "hybrid_min": (0.5, 1), "weno_ao": (0.0, 0)}[recon]
     if solver == "gks":
-        return Params(flux=FLUX_GKS, cfl=0.5, alpha_thres=thres, time_limiter=1, time_scheme=TIME_S2O4, t_end=t_end)
+        return Params(flux=FLUX_GKS, cfl=0.5, alpha_thres=thres, switch_rule=rule, time_limiter=1,
+                      time_scheme=TIME_S2O4, t_end=t_end)
     if solver == "lf":
-        return Params(flux=FLUX_LF, cfl=0.5, alpha_thres=thres, time_scheme=TIME_SSPRK3, t_end=t_end)
+        return Params(flux=FLUX_LF, cfl=0.5, alpha_thres=thres, switch_rule=rule, time_scheme=TIME_SSPRK3,
+                      t_end=t_end)
     raise ValueError(f"unknown solver {solver!r}")
+
+
+def initial_alpha(pr, params, dtype):
+    """alpha^0 from the initial state: the DF product of the Gauss-point values of one evaluation of
+    the spatial operator (with alpha = 1) on the GPU."""
+    import torch
+    from .api import Stepper
+    st = Stepper.for_problem(pr, params, dtype)
+    W = torch.tensor(pr.W, dtype=dtype, device="cuda")
+    A = torch.ones((pr.ny, pr.nx), dtype=dtype, device="cuda")
+    _, _, an = st.rhs(W, A, pr.cfl / _max_signal_speed(pr), want_alpha=True)
+    return an.double().cpu().numpy()
 
 
 def _max_signal_speed(pr) -> float:
@@ -55,7 +73,7 @@ def step_cap(pr) -> int:
     return int(math.ceil(4.0 * t_end / dt0)) + 20
 
 
-def survives(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None):
+def survives(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None, alpha0: str = "one"):
     """Runs the problem at every Mach number of `machs` as one batch; returns [bool] (survived)."""
     import torch
     from .api import Batch
@@ -64,6 +82,11 @@ def survives(problem: str, machs, solver: str, recon: str, n: int | None = None,
     probs = [make(float(m)) if n is None else make(float(m), n=n) for m in machs]
     t_end = probs[0].extra.get("t_end", 0.0)
     params = solver_params(solver, recon, t_end)
+    if alpha0 == "initial":
+        for p in probs:
+            p.alpha = initial_alpha(p, params, dtype)
+    elif alpha0 != "one":
+        raise ValueError(f"unknown alpha0 {alpha0!r}")
     b = Batch([(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y) for p in probs], params, dtype, 0)
     W, A = b.pack([p.W for p in probs], [p.alpha for p in probs])
     nsteps = max(step_cap(p) for p in probs)
@@ -114,7 +137,8 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--problems", default="123,hurricane,rarefaction")
     ap.add_argument("--solvers", default="gks,lf")
-    ap.add_argument("--recons", default="weno_ao,hybrid")
+    ap.add_argument("--recons", default="weno_ao,hybrid,hybrid_min")
+    ap.add_argument("--alpha0", default="one,initial", help="initial DF of the hybrid runs")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--rtol", type=float, default=0.01)
     ap.add_argument("--lo", type=float, default=1.0)
@@ -123,10 +147,12 @@ def main(argv=None) -> int:
     for prob in a.problems.split(","):
         for solver in a.solvers.split(","):
             for recon in a.recons.split(","):
-                t0 = time.time()
-                r = max_mach(prob, solver, recon, lo=a.lo, hi=a.hi, k=a.k, rtol=a.rtol)
-                r["seconds"] = round(time.time() - t0, 2)
-                print(json.dumps(r), flush=True)
+                for alpha0 in (a.alpha0.split(",") if recon != "weno_ao" else ["one"]):
+                    t0 = time.time()
+                    r = max_mach(prob, solver, recon, lo=a.lo, hi=a.hi, k=a.k, rtol=a.rtol, alpha0=alpha0)
+                    r["alpha0"] = alpha0
+                    r["seconds"] = round(time.time() - t0, 2)
+                    print(json.dumps(r), flush=True)
     return 0
 
 
