@@ -77,8 +77,9 @@ typedef struct {
  *                steps taken.  0: exactly nsteps steps [0].  Must be >= 0; dfw_adjoint requires 0.
  *   switch_rule  0: the hybrid switch of eq. (42) as printed, DF quadratic when the largest DF
  *                value of the cell and its two neighbours is below alpha_thres [0]; 1: when the
- *                smallest is (a discontinuity in any of the three cells).  Option for ablations
- *                and the robustness sweeps; the adjoint follows the same rule. */
+ *                smallest is (a discontinuity in any of the three cells); 2: when the cell's own
+ *                value is.  Options for ablations and the robustness sweeps; the adjoint follows
+ *                the same rule. */
 typedef struct {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;

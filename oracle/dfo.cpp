@@ -120,7 +120,8 @@ struct Params {
   int32_t time_limiter; /* 1: eqs. (27)-(29) for the second-stage update */
   int32_t time_scheme;  /* 0: S2O4, eq. (21); 1: SSP-RK3, eq. (32) */
   double t_end;         /* > 0: stop at this time (the last step is shortened to end on it) */
-  int32_t switch_rule;  /* 0: eq. (42) as printed (max of the three DF values); 1: their min (R31) */
+  int32_t switch_rule;  /* 0: eq. (42) as printed (max of the three DF values); 1: their min; 2: the
+                           cell's own value (R31) */
 };
 
 /* ------------------------------------------------------------------------------------------ */
@@ -315,13 +316,16 @@ static T limiter_weight(const T* Q, const Params& prm) {
 }
 
 /* Section 3.3: the hybrid reconstruction of one cell.  a3 = (alpha_{i-1}, alpha_i, alpha_{i+1}).
- * If max(a3) < alpha_thres (strict, eq. (42); with switch_rule 1 the min of a3, reading R31:
- * a discontinuity in any of the three cells) the DF-weighted zero-mean quadratic
+ * If max(a3) < alpha_thres (strict, eq. (42); reading R31 options: switch_rule 1 the min of a3, a
+ * discontinuity in any of the three cells; 2 alpha_i alone, a discontinuity in the cell itself)
+ * the DF-weighted zero-mean quadratic
  *   Q_i + alpha_i [ (Q_{i+1}-Q_i)/dx (x - x0) + (Q_{i-1}/2 - Q_i + Q_{i+1}/2)/dx^2 (x^2 - x1) ],
  * x0 = -dx/2, x1 = dx^2/3, replaces WENO-AO; otherwise WENO-AO.  Coefficients in xi. */
 template <class T>
 static void hybrid_poly(const T* Q, const T* a3, const Params& prm, T* P) {
-  T amax = prm.switch_rule == 1 ? mmin(mmin(a3[0], a3[1]), a3[2]) : mmax(mmax(a3[0], a3[1]), a3[2]);
+  T amax = prm.switch_rule == 1   ? mmin(mmin(a3[0], a3[1]), a3[2])
+           : prm.switch_rule == 2 ? a3[1]
+                                  : mmax(mmax(a3[0], a3[1]), a3[2]);
   if (val(amax) < prm.alpha_thres) {
     const T& al = a3[1];
     T slope = Q[3] - Q[2];

@@ -39,7 +39,7 @@ class Params:
     time_limiter: int = 0  # 1: non-linear time limiter of Section 2.2, eqs. (27)-(29)
     time_scheme: int = TIME_S2O4  # TIME_SSPRK3: eq. (32) of Section 2.3 (LF flux only)
     t_end: float = 0.0  # > 0: stop at this time (the last step is shortened; nsteps is an upper bound)
-    switch_rule: int = 0  # 1: hybrid switch on the min of the three DF values (eq. (42) prints the max)
+    switch_rule: int = 0  # hybrid switch on the max (eq. (42)), 1: min of the three DF values, 2: own cell
 
     def struct(self) -> _lib.dfw_params:
         return _lib.dfw_params(float(self.gamma), float(self.cfl), float(self.dt_fixed), float(self.alpha_thres),

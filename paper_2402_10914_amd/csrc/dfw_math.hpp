@@ -21,19 +21,20 @@ struct Coef {
   real dr[3];     // d_k / d_3
   real inv_d3;
   real K2, k4K2;  // K + 2 and 4 / (K + 2)
-  int sw_min;     // hybrid switch on the min of the three DF values instead of the max
+  int sw_rule;    // hybrid switch: 0 max of the three DF values (eq. (42)), 1 their min, 2 the cell's own
 };
 
 // Eq. (42): the DF quadratic replaces WENO-AO for a cell when the largest DF value of the cell and
-// its two neighbours along the sweep is below the threshold (strict).  sw_min takes the smallest
-// instead (a discontinuity in any of the three cells), a reading kept as an option.
+// its two neighbours along the sweep is below the threshold (strict).  Readings kept as options:
+// sw_rule 1 takes the smallest of the three (a discontinuity in any of them), 2 the cell's own value.
 template <class real>
 DFW_HD inline bool df_switch(real a_lo, real a_c, real a_hi, const Coef<real>& k) {
   real mx = a_lo > a_c ? a_lo : a_c;
   mx = mx > a_hi ? mx : a_hi;
   real mn = a_lo < a_c ? a_lo : a_c;
   mn = mn < a_hi ? mn : a_hi;
-  return (k.sw_min ? mn : mx) < k.alpha_thres;
+  const real a = k.sw_rule == 1 ? mn : (k.sw_rule == 2 ? a_c : mx);
+  return a < k.alpha_thres;
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -60,7 +60,7 @@ struct Scheme {
   int tl;  // non-linear time limiter (eqs. (27)-(29)) on
   int ts;  // time scheme: DFW_TIME_S2O4 (eq. (21)) or DFW_TIME_SSPRK3 (eq. (32))
   double t_end;  // > 0: stop at this time
-  int sw;        // hybrid switch rule (0: max of the three DF values, eq. (42); 1: min)
+  int sw;        // hybrid switch rule (0: max of the three DF values, eq. (42); 1: min; 2: own cell)
 };
 
 // OUT_OMEGA: time-limiter weight of each interface: with OUT_F (first stage) stored in plane 9, without
@@ -84,7 +84,7 @@ __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
   k.inv_d3 = real(1.0 / S.d[3]);
   k.K2 = real(S.K + 2.0);
   k.k4K2 = real(4.0 / (S.K + 2.0));
-  k.sw_min = S.sw;
+  k.sw_rule = S.sw;
   return k;
 }
 
@@ -766,7 +766,7 @@ static dfw_status check_params(const dfw_params* p, int32_t dtype) {
   if (p->time_scheme == DFW_TIME_SSPRK3 && (p->flux != DFW_FLUX_LF || p->time_limiter))
     return fail(DFW_EINVAL, "SSP-RK3 runs with the LF flux and without the time limiter");
   if (!(p->t_end >= 0.0)) return fail(DFW_EINVAL, "t_end must be >= 0 (0: no end time)");
-  if (p->switch_rule != 0 && p->switch_rule != 1) return fail(DFW_EINVAL, "switch_rule must be 0 or 1");
+  if (p->switch_rule < 0 || p->switch_rule > 2) return fail(DFW_EINVAL, "switch_rule must be 0, 1 or 2");
   if (dtype != DFW_F64 && dtype != DFW_F32) return fail(DFW_EDTYPE, "dtype must be DFW_F64 or DFW_F32");
   return DFW_OK;
 }

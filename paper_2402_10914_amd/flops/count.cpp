@@ -47,7 +47,7 @@ static dfw::Coef<C> coef() {
   for (int i = 0; i < 3; ++i) k.dr[i] = d[i] / d[3];
   k.inv_d3 = 1 / d[3];
   k.K2 = k.K.v + 2; k.k4K2 = 4 / (k.K.v + 2);
-  k.sw_min = 0;
+  k.sw_rule = 0;
   return k;
 }
 

@@ -7,7 +7,8 @@ Schemes, the paper's two solvers: ``gks`` = S2O4 with the gas-kinetic flux and t
 time limiter (eqs. (21), (27)-(29)); ``lf`` = SSP-RK3 with the Lax-Friedrichs flux (eq. (32)).
 Reconstructions: ``weno_ao`` (DF threshold 0: the switch never engages), ``hybrid`` (threshold 0.5,
 the switch of eq. (42) as printed: the largest DF value of the three cells below the threshold) and
-``hybrid_min`` (the same with the smallest of the three).  Initial DF: ``one`` (alpha^0 = 1) or
+``hybrid_min`` (the same with the smallest of the three) and ``hybrid_own`` (the cell's own DF
+value).  Initial DF: ``one`` (alpha^0 = 1) or
 ``initial`` (the DF product of the initial state's own Gauss-point values, one evaluation of the
 operator before the first step).  CFL 0.5, as the paper uses for these problems.
 
@@ -26,13 +27,13 @@ import numpy as np
 from . import workloads as WL
 
 SOLVERS = ("gks", "lf")
-RECONS = ("weno_ao", "hybrid", "hybrid_min")
+RECONS = ("weno_ao", "hybrid", "hybrid_min", "hybrid_own")
 ALPHA0 = ("one", "initial")
 
 
 def solver_params(solver: str, recon: str, t_end: float = 0.0):
     from .api import FLUX_GKS, FLUX_LF, TIME_S2O4, TIME_SSPRK3, Params
-    thres, rule = {"hybrid": (0.5, 0), "hybrid_min": (0.5, 1), "weno_ao": (0.0, 0)}[recon]
+    thres, rule = {"hybrid": (0.5, 0), "hybrid_min": (0.5, 1), "hybrid_own": (0.5, 2), "weno_ao": (0.0, 0)}[recon]
     if solver == "gks":
         return Params(flux=FLUX_GKS, cfl=0.5, alpha_thres=thres, switch_rule=rule, time_limiter=1,
                       time_scheme=TIME_S2O4, t_end=t_end)
@@ -137,7 +138,7 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--problems", default="123,hurricane,rarefaction")
     ap.add_argument("--solvers", default="gks,lf")
-    ap.add_argument("--recons", default="weno_ao,hybrid,hybrid_min")
+    ap.add_argument("--recons", default="weno_ao,hybrid,hybrid_min,hybrid_own")
     ap.add_argument("--alpha0", default="one,initial", help="initial DF of the hybrid runs")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--rtol", type=float, default=0.01)

@@ -29,7 +29,7 @@ static Coef<real> coef(double alpha_thres = 0.5, double c1 = 0.01, double c2 = 5
   k.inv_d3 = 1 / d[3];
   k.K2 = k.K + 2;
   k.k4K2 = 4 / (k.K + 2);
-  k.sw_min = 0;
+  k.sw_rule = 0;
   return k;
 }
 

@@ -83,7 +83,7 @@ def test_workspace_bytes_host_only():
     (dict(params=_params(time_scheme=1, flux=1)), _lib.DFW_EINVAL),  # SSP-RK3 runs with LF only
     (dict(params=_params(time_scheme=1, time_limiter=1)), _lib.DFW_EINVAL),
     (dict(params=_params(t_end=-1.0)), _lib.DFW_EINVAL),
-    (dict(params=_params(switch_rule=2)), _lib.DFW_EINVAL),
+    (dict(params=_params(switch_rule=3)), _lib.DFW_EINVAL),
     (dict(dtype=5), _lib.DFW_EDTYPE),
     (dict(W=None), _lib.DFW_EINVAL),
     (dict(nsteps=-1), _lib.DFW_EINVAL),

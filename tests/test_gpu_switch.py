@@ -1,4 +1,4 @@
-"""The min reading of the hybrid switch (option switch_rule = 1; eq. (42) prints the max) on the GPU
+"""The min and own-cell readings of the hybrid switch (switch_rule 1, 2; eq. (42) prints the max) on the GPU
 against the oracle, through the C ABI: the spatial operator with DF fields that engage the two rules
 differently, runs of the 123 problem with the initial DF taken from the initial state, and the
 adjoint (same branch rule) against the oracle's forward-mode derivative."""
@@ -39,7 +39,7 @@ def test_rhs_parity_under_both_rules(flux):
     g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
     dt = 0.4 / O.max_speed(pr.W, g, O.make_params())[0]
     out = {}
-    for rule in (0, 1):
+    for rule in (0, 1, 2):
         Lo, Lto, ao = O.rhs(pr.W, alpha, g, O.make_params(flux=flux, switch_rule=rule), dt, want_alpha=True)
         st = api.Stepper.for_problem(pr, api.Params(flux=flux, switch_rule=rule), torch.float64)
         L, Lt, an = st.rhs(torch.tensor(pr.W, device="cuda"), torch.tensor(alpha, device="cuda"), dt, want_alpha=True)
@@ -48,20 +48,21 @@ def test_rhs_parity_under_both_rules(flux):
         assert np.abs(Lt - Lto).sum() * dt <= 1e-12 * np.abs(Lo).sum()
         assert _rel_l1(an, ao) <= 1e-12
         out[rule] = L
-    assert _rel_l1(out[1], out[0]) > 1e-6  # the rules differ on this DF field
+    assert _rel_l1(out[1], out[0]) > 1e-6 and _rel_l1(out[2], out[1]) > 1e-6  # the rules differ here
 
 
+@pytest.mark.parametrize("rule", [1, 2])
 @pytest.mark.parametrize("kw,nsteps", [(dict(flux=0, time_scheme=1), 40), (dict(flux=1), 25),
                                        (dict(flux=1, time_limiter=1), 5)])
-def test_123_problem_min_rule_run_matches_oracle(kw, nsteps):
+def test_123_problem_run_matches_oracle(kw, nsteps, rule):
     api = _api()
     pr = WL.problem_123(6.0)
     g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
-    P = O.make_params(cfl=0.5, switch_rule=1, **kw)
+    P = O.make_params(cfl=0.5, switch_rule=rule, **kw)
     dt0 = 0.5 / O.max_speed(pr.W, g, P)[0]
     _, _, a0 = O.rhs(pr.W, pr.alpha, g, P, dt0, want_alpha=True)  # DF of the initial state
     Wo, Ao, to, dto, fso = O.run(pr.W, a0, g, P, nsteps)
-    st = api.Stepper.for_problem(pr, api.Params(cfl=0.5, switch_rule=1, **kw), torch.float64)
+    st = api.Stepper.for_problem(pr, api.Params(cfl=0.5, switch_rule=rule, **kw), torch.float64)
     W = torch.tensor(pr.W, device="cuda")
     A = torch.tensor(pr.alpha, device="cuda")
     _, _, A0 = st.rhs(W, A, dt0, want_alpha=True)
@@ -79,8 +80,9 @@ def test_123_problem_min_rule_run_matches_oracle(kw, nsteps):
     assert _rel_l1(A.cpu().numpy(), Ao) <= 1e-12
 
 
+@pytest.mark.parametrize("rule", [1, 2])
 @pytest.mark.parametrize("flux", [0, 1])
-def test_adjoint_under_the_min_rule_matches_oracle(flux):
+def test_adjoint_under_the_switch_rules_matches_oracle(flux, rule):
     api = _api()
     pr = WL.density_wave(7, 6)
     rng = np.random.default_rng(73)
@@ -90,14 +92,14 @@ def test_adjoint_under_the_min_rule_matches_oracle(flux):
     dt = 0.4 / O.max_speed(pr.W, g, O.make_params())[0]
     nsteps = 2
     gW, gA = rng.standard_normal((4, 6, 7)), rng.standard_normal((6, 7))
-    st = api.Stepper.for_problem(pr, api.Params(flux=flux, dt_fixed=dt, switch_rule=1))
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, dt_fixed=dt, switch_rule=rule))
     adj = api.Adjoint(st, nsteps, 1)
     W = torch.tensor(pr.W, device="cuda")
     A = torch.tensor(pr.alpha, device="cuda")
     assert adj.forward(W, A)[1] == -1
     gW0, gA0 = adj.backward(torch.tensor(gW, device="cuda"), torch.tensor(gA, device="cuda"))
     gW0, gA0 = gW0.cpu().numpy(), gA0.cpu().numpy()
-    P = O.make_params(flux=flux, dt_fixed=dt, switch_rule=1)
+    P = O.make_params(flux=flux, dt_fixed=dt, switch_rule=rule)
     for s in range(6):  # random directions: <g, J v> against the oracle's forward mode
         vW, vA = rng.standard_normal((4, 6, 7)), rng.standard_normal((6, 7))
         _, _, dW, dA = O.run_tangent(pr.W, pr.alpha, vW, vA, g, P, [dt] * nsteps)

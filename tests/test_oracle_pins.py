@@ -144,6 +144,20 @@ def test_hybrid_switch_rule_min():
     np.testing.assert_allclose(O.hybrid(Q, [0.5, 0.7, 0.5], p1), wa, atol=0)     # strict: min == threshold
 
 
+def test_hybrid_switch_rule_own_cell():
+    """Reading R31 (switch_rule 2): the DF quadratic exactly when the cell's own DF is below the
+    threshold, whatever its neighbours hold."""
+    rng = np.random.default_rng(5)
+    Q = rng.normal(size=5)
+    p0, p2 = O.make_params(alpha_thres=0.5), O.make_params(alpha_thres=0.5, switch_rule=2)
+    wa = O.weno_ao(Q, p0)
+    dfq = O.hybrid(Q, [0.1, 0.3, 0.2], p0)                                          # p_DF with alpha_i = 0.3
+    np.testing.assert_allclose(O.hybrid(Q, [1.0, 0.3, 1.0], p2), dfq, atol=0)
+    np.testing.assert_allclose(O.hybrid(Q, [0.1, 0.3, 0.2], p2), dfq, atol=0)
+    np.testing.assert_allclose(O.hybrid(Q, [0.1, 0.9, 0.2], p2), wa, atol=0)       # neighbours alone: WENO-AO
+    np.testing.assert_allclose(O.hybrid(Q, [0.1, 0.5, 0.2], p2), wa, atol=0)       # strict
+
+
 # ----------------------------------------------------------------------------------------------
 # Characteristic basis, fluxes
 # ----------------------------------------------------------------------------------------------
