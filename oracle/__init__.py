@@ -45,7 +45,8 @@ class Params(ctypes.Structure):
                 ("alpha_thres", ctypes.c_double), ("d_h", ctypes.c_double), ("d_l", ctypes.c_double),
                 ("eps_weno", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("flux", ctypes.c_int32), ("time_limiter", ctypes.c_int32), ("time_scheme", ctypes.c_int32),
-                ("t_end", ctypes.c_double), ("switch_rule", ctypes.c_int32)]
+                ("t_end", ctypes.c_double), ("switch_rule", ctypes.c_int32), ("componentwise", ctypes.c_int32),
+                ("df_stage", ctypes.c_int32)]
 
 
 _lib = None
@@ -90,10 +91,10 @@ def make_grid(nx, ny, dx, dy, bc_x=BC_PERIODIC, bc_y=None) -> Grid:
 
 def make_params(flux=FLUX_LF, gamma=1.4, cfl=0.5, dt_fixed=0.0, alpha_thres=0.5, d_h=0.85, d_l=0.85,
                 eps_weno=1e-6, c1=0.01, c2=5.0, time_limiter=0, time_scheme=TIME_S2O4, t_end=0.0,
-                switch_rule=0) -> Params:
+                switch_rule=0, componentwise=0, df_stage=0) -> Params:
     return Params(float(gamma), float(cfl), float(dt_fixed), float(alpha_thres), float(d_h), float(d_l),
                   float(eps_weno), float(c1), float(c2), int(flux), int(time_limiter), int(time_scheme),
-                  float(t_end), int(switch_rule))
+                  float(t_end), int(switch_rule), int(componentwise), int(df_stage))
 
 
 def max_speed(W: np.ndarray, grid: Grid, params: Params):

@@ -122,6 +122,8 @@ struct Params {
   double t_end;         /* > 0: stop at this time (the last step is shortened to end on it) */
   int32_t switch_rule;  /* 0: eq. (42) as printed (max of the three DF values); 1: their min; 2: the
                            cell's own value (R31) */
+  int32_t componentwise; /* 1: reconstruct the conservative variables component by component (R1) */
+  int32_t df_stage;      /* 1: alpha^{n+1} from the first stage's Gauss points (R5) */
 };
 
 /* ------------------------------------------------------------------------------------------ */
@@ -159,6 +161,12 @@ static void invert(int n, const T* A, T* Ainv) {
     solve_linear(n, A, e, col);
     for (int i = 0; i < n; ++i) Ainv[i * n + j] = col[i];
   }
+}
+
+/* (R1 ablation) the identity in place of both bases: component-wise reconstruction. */
+template <class T>
+static void identity4(T* R, T* L) {
+  for (int i = 0; i < 16; ++i) R[i] = L[i] = T(i % 5 == 0 ? 1.0 : 0.0);
 }
 
 template <class T>
@@ -771,6 +779,7 @@ static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Gri
       W(f, t, w1);
       for (int c = 0; c < 4; ++c) wm[c] = 0.5 * (w0[c] + w1[c]);
       char_basis(fr, wm, gamma, R, L);
+      if (prm.componentwise) identity4(R, L);
       T Q[6][4];
       for (int k = 0; k < 6; ++k) {
         T w[4];
@@ -828,6 +837,7 @@ static void sweep(int dir, const Ghosted<T>& Wg, const Ghosted<T>& Ag, const Gri
       W(f, t, w1);
       for (int c = 0; c < 4; ++c) wm[c] = 0.5 * (w0[c] + w1[c]);
       char_basis(fr, wm, gamma, R, L);
+      if (prm.componentwise) identity4(R, L);
       T gpW[2][2][4], gpWt[2][2][4], gpWn[2][4]; /* [side][gp][comp] */
       for (int side = 0; side < 2; ++side) {
         const std::vector<T>& line = side == 0 ? lineL : lineR;
@@ -977,9 +987,11 @@ template <class T>
 static void s2o4_limited_step(T* W, T* alpha, const Grid& G, const Params& prm, double dt) {
   const size_t N = (size_t)G.nx * G.ny, n = 4 * N;
   std::vector<T> L0(n), Lt0(n), Lt0l(n), Ws(n), L1(n), Lt1(n), Lt1l(n), an(N);
-  spatial_operator(W, alpha, G, prm, dt, L0.data(), Lt0.data(), (T*)nullptr, Lt0l.data());
+  T* a_first = prm.df_stage ? an.data() : (T*)nullptr; /* R5: the DF from the last stage unless df_stage */
+  T* a_last = prm.df_stage ? (T*)nullptr : an.data();
+  spatial_operator(W, alpha, G, prm, dt, L0.data(), Lt0.data(), a_first, Lt0l.data());
   for (size_t k = 0; k < n; ++k) Ws[k] = W[k] + 0.5 * dt * L0[k] + (dt * dt / 8.0) * Lt0[k];
-  spatial_operator(Ws.data(), alpha, G, prm, dt, L1.data(), Lt1.data(), an.data(), Lt1l.data());
+  spatial_operator(Ws.data(), alpha, G, prm, dt, L1.data(), Lt1.data(), a_last, Lt1l.data());
   for (size_t k = 0; k < n; ++k)
     W[k] = W[k] + dt * L0[k] + (dt * dt / 2.0) * Lt0[k] - (dt * dt / 3.0) * Lt0l[k] + (dt * dt / 3.0) * Lt1l[k];
   for (size_t k = 0; k < N; ++k) alpha[k] = an[k];
@@ -991,8 +1003,9 @@ static void s2o4_step(T* W, T* alpha, const Grid& G, const Params& prm, double d
   const size_t N = (size_t)G.nx * G.ny;
   std::vector<T> an(N);
   s2o4(W, 4 * N, dt, [&](const T* w, T* L, T* Lt, int stage) {
-    /* alpha^n in both stages (R6); alpha^{n+1} from the second stage's Gauss points (R5) */
-    spatial_operator(w, alpha, G, prm, dt, L, Lt, stage == 1 ? an.data() : (T*)nullptr);
+    /* alpha^n in both stages (R6); alpha^{n+1} from the second stage's Gauss points (R5; the
+     * first stage's with df_stage) */
+    spatial_operator(w, alpha, G, prm, dt, L, Lt, stage == (prm.df_stage ? 0 : 1) ? an.data() : (T*)nullptr);
   });
   for (size_t k = 0; k < N; ++k) alpha[k] = an[k];
 }
@@ -1020,7 +1033,7 @@ static void ssprk3_step(T* W, T* alpha, const Grid& G, const Params& prm, double
   ssprk3(W, 4 * N, dt, [&](const T* w, T* L, int stage) {
     /* (R29) alpha^n in all stages; alpha^{n+1} from the third stage's Gauss points.  Only L enters
      * eq. (32); the time derivative the operator also returns is discarded. */
-    spatial_operator(w, alpha, G, prm, dt, L, Lt.data(), stage == 2 ? an.data() : (T*)nullptr);
+    spatial_operator(w, alpha, G, prm, dt, L, Lt.data(), stage == (prm.df_stage ? 0 : 2) ? an.data() : (T*)nullptr);
   });
   for (size_t k = 0; k < N; ++k) alpha[k] = an[k];
 }
@@ -1049,13 +1062,13 @@ struct dfo_params {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux, time_limiter, time_scheme;
   double t_end;
-  int32_t switch_rule;
+  int32_t switch_rule, componentwise, df_stage;
 };
 
 static Grid to_grid(const dfo_grid* g) { return Grid{g->nx, g->ny, g->dx, g->dy, g->bc_x, g->bc_y}; }
 static Params to_params(const dfo_params* p) {
   return Params{p->gamma, p->cfl, p->dt_fixed, p->alpha_thres, p->d_h, p->d_l, p->eps_weno, p->c1, p->c2, p->flux,
-                p->time_limiter, p->time_scheme, p->t_end, p->switch_rule};
+                p->time_limiter, p->time_scheme, p->t_end, p->switch_rule, p->componentwise, p->df_stage};
 }
 
 /* 0 on success, 1 when the state holds a non-positive density/pressure or a non-finite value. */

@@ -840,3 +840,50 @@ def test_t_end_stops_exactly_and_matches_the_exact_solution():
     Wu, _, tu, _, _ = O.run(pr.W, pr.alpha, g, O.make_params(dt_fixed=0.3 / k), k)
     err_u = np.abs(Wu[0] - WL.density_wave_avg(32, 32, t=tu)).mean()
     assert 0.8 * err_u <= err <= 1.25 * err_u, (err, err_u)
+
+
+# ----------------------------------------------------------------------------------------------
+# Ablations: component-wise reconstruction (R1) and the DF source stage (R5)
+# ----------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("flux", [O.FLUX_LF, O.FLUX_GKS])
+def test_componentwise_equals_characteristic_on_the_density_wave(flux):
+    """All conservative components of the advected wave are affine in rho and its variation lies on
+    one eigenvector, so both reconstructions give the same states (up to rounding); on Riemann data
+    they differ; both conserve."""
+    pr = WL.density_wave(24)
+    g = O.make_grid(24, 24, pr.dx, pr.dy)
+    A = O.run(pr.W, pr.alpha, g, O.make_params(flux=flux, cfl=0.5), 5)[0]
+    B = O.run(pr.W, pr.alpha, g, O.make_params(flux=flux, cfl=0.5, componentwise=1), 5)[0]
+    np.testing.assert_allclose(B, A, rtol=0, atol=1e-12 * np.abs(A).max())
+    pr, g, _ = _riemann_small(n=32, flux=flux, steps=4)
+    pc = O.make_params(flux=flux, cfl=0.4, componentwise=1)
+    C = O.run(pr.W, pr.alpha, g, O.make_params(flux=flux, cfl=0.4), 4)[0]
+    D, _, _, _, fs = O.run(pr.W, pr.alpha, g, pc, 4)
+    assert fs == -1 and np.abs(C - D).max() > 1e-6
+    pr = WL.circles(48, ncirc=5, flux=flux)
+    gp = O.make_grid(48, 48, pr.dx, pr.dy)
+    E, _, _, _, fs = O.run(pr.W, pr.alpha, gp, pc, 3)
+    assert fs == -1
+    assert np.all(np.abs(E.sum(axis=(1, 2)) - pr.W.sum(axis=(1, 2))) <= 1e-13 * np.abs(pr.W).sum(axis=(1, 2)))
+
+
+@pytest.mark.parametrize("flux", [O.FLUX_LF, O.FLUX_GKS])
+def test_df_source_stage(flux):
+    """R5: after one S2O4 step alpha^{n+1} is the operator's DF product at W* = W + dt/2 L + dt^2/8 L_t
+    (default) or at W^n (df_stage = 1); with SSP-RK3 and df_stage = 1, at W^n as well."""
+    pr, g, _ = _riemann_small(n=24, flux=flux, steps=1)
+    alpha = np.random.default_rng(6).uniform(0.3, 1.0, pr.alpha.shape)
+    for df_stage in (0, 1):
+        P = O.make_params(flux=flux, cfl=0.4, df_stage=df_stage)
+        W1, a1, _, dth, fs = O.run(pr.W, alpha, g, P, 1)
+        dt = dth[0]
+        L, Lt, a_n = O.rhs(pr.W, alpha, g, P, dt, want_alpha=True)
+        Ws = pr.W + 0.5 * dt * L + (dt * dt / 8.0) * Lt
+        _, _, a_s = O.rhs(Ws, alpha, g, P, dt, want_alpha=True)
+        want = a_n if df_stage else a_s
+        np.testing.assert_allclose(a1, want, rtol=1e-13, atol=1e-15)
+        assert np.abs(a_n - a_s).max() > 1e-6  # the two readings differ here
+    P = O.make_params(flux=O.FLUX_LF, cfl=0.4, time_scheme=O.TIME_SSPRK3, df_stage=1)
+    _, a1, _, dth, _ = O.run(pr.W, alpha, g, P, 1)
+    np.testing.assert_array_equal(a1, O.rhs(pr.W, alpha, g, P, dth[0], want_alpha=True)[2])
