@@ -79,7 +79,12 @@ typedef struct {
  *                value of the cell and its two neighbours is below alpha_thres [0]; 1: when the
  *                smallest is (a discontinuity in any of the three cells); 2: when the cell's own
  *                value is.  Options for ablations and the robustness sweeps; the adjoint follows
- *                the same rule. */
+ *                the same rule.
+ *   componentwise 0: reconstruct characteristic variables (eigenvectors of the normal flux
+ *                Jacobian at the mean of the two cells beside each interface) [0]; 1: reconstruct
+ *                the conservative variables component by component (ablation).
+ *   df_stage     0: alpha^{n+1} from the Gauss-point states of the last stage [0]; 1: from the
+ *                first stage's (the states of W^n; ablation).  dfw_adjoint requires both 0. */
 typedef struct {
   double gamma, cfl, dt_fixed, alpha_thres, d_h, d_l, eps_weno, c1, c2;
   int32_t flux;
@@ -88,6 +93,8 @@ typedef struct {
   int32_t time_scheme;
   double t_end;
   int32_t switch_rule;
+  int32_t componentwise;
+  int32_t df_stage;
 } dfw_params;
 
 /* Bytes of device workspace needed by dfw_run / dfw_rhs / dfw_max_speed for this grid. */

@@ -33,7 +33,7 @@ class dfw_params(ctypes.Structure):
                 ("eps_weno", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("flux", ctypes.c_int32), ("tile", ctypes.c_int32), ("time_limiter", ctypes.c_int32),
                 ("time_scheme", ctypes.c_int32), ("t_end", ctypes.c_double),
-                ("switch_rule", ctypes.c_int32)]
+                ("switch_rule", ctypes.c_int32), ("componentwise", ctypes.c_int32), ("df_stage", ctypes.c_int32)]
 
 
 class DFWError(RuntimeError):

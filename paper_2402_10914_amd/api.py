@@ -40,12 +40,15 @@ class Params:
     time_scheme: int = TIME_S2O4  # TIME_SSPRK3: eq. (32) of Section 2.3 (LF flux only)
     t_end: float = 0.0  # > 0: stop at this time (the last step is shortened; nsteps is an upper bound)
     switch_rule: int = 0  # hybrid switch on the max (eq. (42)), 1: min of the three DF values, 2: own cell
+    componentwise: int = 0  # 1: reconstruct conservative variables component by component (ablation)
+    df_stage: int = 0  # 1: alpha^{n+1} from the first stage's Gauss points (ablation)
 
     def struct(self) -> _lib.dfw_params:
         return _lib.dfw_params(float(self.gamma), float(self.cfl), float(self.dt_fixed), float(self.alpha_thres),
                                float(self.d_h), float(self.d_l), float(self.eps_weno), float(self.c1),
                                float(self.c2), int(self.flux), int(self.tile), int(self.time_limiter),
-                               int(self.time_scheme), float(self.t_end), int(self.switch_rule))
+                               int(self.time_scheme), float(self.t_end), int(self.switch_rule),
+                               int(self.componentwise), int(self.df_stage))
 
 
 def tile_shapes():

@@ -91,6 +91,37 @@ DFW_HD void unproject(const Basis<real>& B, const real* q, real* w) {
   w[3] = B.H * (q[0] + q[3]) + B.u * B.c * dq + B.hq2 * q[1] + B.v * q[2];
 }
 
+// The variables the reconstruction works on: characteristic (CHAR) or, as an ablation of that
+// choice, the conservative variables themselves (component-wise reconstruction).
+template <bool CHAR, class real>
+DFW_HD void to_recon(const Basis<real>& B, const real* w, real* q) {
+  if constexpr (CHAR) {
+    project(B, w, q);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q[c] = w[c];
+  }
+}
+
+template <bool CHAR, class real>
+DFW_HD void from_recon(const Basis<real>& B, const real* q, real* w) {
+  if constexpr (CHAR) {
+    unproject(B, q, w);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = q[c];
+  }
+}
+
+template <bool CHAR, class real>
+DFW_HD Basis<real> recon_basis(const real* wa, const real* wb, const Coef<real>& k) {
+  if constexpr (CHAR) {
+    return make_basis(wa, wb, k);
+  } else {
+    return Basis<real>{};
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Hybrid reconstruction of one cell (Section 3.1 and 3.3).  Q[0..4] = Q_{i-2..i+2}; the result is
 // the polynomial P(xi) = sum_n P[n] xi^n on the cell, xi = (x - x_{i+1/2})/dx in [-1, 0].
@@ -212,12 +243,12 @@ DFW_HD real time_limiter_weight(const real* Q, const Coef<real>& k) {
 
 // Weight omega of an interface: the smallest weight over the characteristic components of the two
 // normal reconstructions beside it (cells 2 and 3 of its six-cell row, each with its own stencil).
-template <class real>
+template <class real, bool CHAR = true>
 DFW_HD real time_limiter_omega(const real (*cell)[4], const Coef<real>& k) {
-  Basis<real> B = make_basis(cell[2], cell[3], k);
+  const Basis<real> B = recon_basis<CHAR>(cell[2], cell[3], k);
   real Q[6][4];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) project(B, cell[m], Q[m]);
+  for (int m = 0; m < 6; ++m) to_recon<CHAR>(B, cell[m], Q[m]);
   real om = real(1);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -515,13 +546,13 @@ DFW_HD void gks_flux(const real* wl, const real* wln, const real* wlt, const rea
 // left state (cell f-1 at its right edge) and the right state (cell f at its left edge, mirrored
 // stencil) and their normal derivatives, in conservative variables.
 // ------------------------------------------------------------------------------------------------
-template <class real>
+template <class real, bool CHAR = true>
 DFW_HD void normal_sweep(const real (*cell)[4], real a0, real a1, real a2, real a3, real inv_dn,
                          const Coef<real>& k, real* wl, real* wr, real* wln, real* wrn) {
-  Basis<real> B = make_basis(cell[2], cell[3], k);
+  const Basis<real> B = recon_basis<CHAR>(cell[2], cell[3], k);
   real Q[6][4];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) project(B, cell[m], Q[m]);
+  for (int m = 0; m < 6; ++m) to_recon<CHAR>(B, cell[m], Q[m]);
   real ql[4], qld[4], qr[4], qrd[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -537,10 +568,10 @@ DFW_HD void normal_sweep(const real (*cell)[4], real a0, real a1, real a2, real 
     qr[c] = P2[0];
     qrd[c] = -P2[1] * inv_dn;
   }
-  unproject(B, ql, wl);
-  unproject(B, qr, wr);
-  unproject(B, qld, wln);
-  unproject(B, qrd, wrn);
+  from_recon<CHAR>(B, ql, wl);
+  from_recon<CHAR>(B, qr, wr);
+  from_recon<CHAR>(B, qld, wln);
+  from_recon<CHAR>(B, qrd, wrn);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -550,11 +581,11 @@ DFW_HD void normal_sweep(const real (*cell)[4], real a0, real a1, real a2, real 
 // the two Gauss points of the flux and its time derivative (quadrature weights applied by the
 // caller) and the product of the two Gauss-point DF values.
 // ------------------------------------------------------------------------------------------------
-template <class real, int FLUX, bool WANT_F, bool WANT_DF, class LineFn>
+template <class real, int FLUX, bool WANT_F, bool WANT_DF, bool CHAR = true, class LineFn>
 DFW_HD void segment_fluxes(const real* wa, const real* wb, LineFn line, const real (*alpha)[3],
                            const real* wln, const real* wrn, real dt, real inv_dt, const Coef<real>& k,
                            real* Fs, real* Fts, real& dfp) {
-  Basis<real> B = make_basis(wa, wb, k);
+  const Basis<real> B = recon_basis<CHAR>(wa, wb, k);
   real gw[2][2][4], gwt[2][2][4];  // [side][gauss point][component]
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -564,7 +595,7 @@ DFW_HD void segment_fluxes(const real* wa, const real* wb, LineFn line, const re
       real w[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) w[c] = line(side, m, c);
-      project(B, w, Q[m]);
+      to_recon<CHAR>(B, w, Q[m]);
     }
     real qv[2][4], qd[2][4];
 #pragma unroll
@@ -583,8 +614,8 @@ DFW_HD void segment_fluxes(const real* wa, const real* wb, LineFn line, const re
     }
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
-      unproject(B, qv[g], gw[side][g]);
-      unproject(B, qd[g], gwt[side][g]);
+      from_recon<CHAR>(B, qv[g], gw[side][g]);
+      from_recon<CHAR>(B, qd[g], gwt[side][g]);
     }
   }
 #pragma unroll

@@ -61,6 +61,8 @@ struct Scheme {
   int ts;  // time scheme: DFW_TIME_S2O4 (eq. (21)) or DFW_TIME_SSPRK3 (eq. (32))
   double t_end;  // > 0: stop at this time
   int sw;        // hybrid switch rule (0: max of the three DF values, eq. (42); 1: min; 2: own cell)
+  int cw;        // 1: component-wise reconstruction of the conservative variables (ablation)
+  int dfs;       // 1: alpha^{n+1} from the first stage's Gauss points instead of the last stage's
 };
 
 // OUT_OMEGA: time-limiter weight of each interface: with OUT_F (first stage) stored in plane 9, without
@@ -238,7 +240,12 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
 #pragma unroll
       for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][rr][fl + m];
     real wl[4], wr[4];
-    normal_sweep<real>(cell, sA[rr][fl], sA[rr][fl + 1], sA[rr][fl + 2], sA[rr][fl + 3], inv_dn, k, wl, wr, wln, wrn);
+    if (S.cw)  // uniform over the launch
+      normal_sweep<real, false>(cell, sA[rr][fl], sA[rr][fl + 1], sA[rr][fl + 2], sA[rr][fl + 3], inv_dn, k, wl, wr,
+                                wln, wrn);
+    else
+      normal_sweep<real, true>(cell, sA[rr][fl], sA[rr][fl + 1], sA[rr][fl + 2], sA[rr][fl + 3], inv_dn, k, wl, wr,
+                               wln, wrn);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       sLine[c][tid] = wl[c];
@@ -263,8 +270,12 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
     for (int q = 0; q < 3; ++q) al[side][q] = sA[rr - 1 + q][fl + 1 + side];
   auto line = [&](int side, int m, int c) -> real { return sLine[4 * side + c][tid + (m - 2) * rstride]; };
   real Fs[4], Fts[4], dfp;
-  segment_fluxes<real, FLUX, (OUT & OUT_F) != 0, (OUT & OUT_DF) != 0>(wa, wb, line, al, wln, wrn, dt, inv_dt, k, Fs,
-                                                                        Fts, dfp);
+  if (S.cw)
+    segment_fluxes<real, FLUX, (OUT & OUT_F) != 0, (OUT & OUT_DF) != 0, false>(wa, wb, line, al, wln, wrn, dt, inv_dt,
+                                                                               k, Fs, Fts, dfp);
+  else
+    segment_fluxes<real, FLUX, (OUT & OUT_F) != 0, (OUT & OUT_DF) != 0, true>(wa, wb, line, al, wln, wrn, dt, inv_dt,
+                                                                              k, Fs, Fts, dfp);
   real om = real(1);
   if (OUT & OUT_OMEGA) {  // eq. (29), from the six cells of this segment's row
     real cell[6][4];
@@ -272,7 +283,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
     for (int m = 0; m < 6; ++m)
 #pragma unroll
       for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][rr][fl + m];
-    om = time_limiter_omega(cell, k);
+    om = S.cw ? time_limiter_omega<real, false>(cell, k) : time_limiter_omega<real, true>(cell, k);
   }
   // ---- write face sums (quadrature weights 1/2), components back to the global order
   const size_t fstride = dir == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
@@ -711,6 +722,11 @@ static void launch_faces(const FaceLaunch& L, const real* W, const real* A, real
   if (L.out == OUT_F) launch_faces_shape<real, DFW_FLUX_LF, OUT_F>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_F | OUT_DF)) launch_faces_shape<real, DFW_FLUX_LF, OUT_F | OUT_DF>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_F | OUT_FT)) launch_faces_out<real, OUT_F | OUT_FT>(L, W, A, FX, FY, st);
+  // the DF taken from the first stage (df_stage = 1): the second stage writes no DF
+  else if (L.out == OUT_FT) launch_faces_out<real, OUT_FT>(L, W, A, FX, FY, st);
+  else if (L.out == (OUT_FT | OUT_OMEGA)) launch_faces_out<real, OUT_FT | OUT_OMEGA>(L, W, A, FX, FY, st);
+  else if (L.out == (OUT_F | OUT_FT | OUT_DF | OUT_OMEGA))
+    launch_faces_out<real, OUT_F | OUT_FT | OUT_DF | OUT_OMEGA>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_FT | OUT_DF)) launch_faces_out<real, OUT_FT | OUT_DF>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_F | OUT_FT | OUT_OMEGA)) launch_faces_out<real, OUT_F | OUT_FT | OUT_OMEGA>(L, W, A, FX, FY, st);
   else if (L.out == (OUT_FT | OUT_DF | OUT_OMEGA))
@@ -767,6 +783,8 @@ static dfw_status check_params(const dfw_params* p, int32_t dtype) {
     return fail(DFW_EINVAL, "SSP-RK3 runs with the LF flux and without the time limiter");
   if (!(p->t_end >= 0.0)) return fail(DFW_EINVAL, "t_end must be >= 0 (0: no end time)");
   if (p->switch_rule < 0 || p->switch_rule > 2) return fail(DFW_EINVAL, "switch_rule must be 0, 1 or 2");
+  if (p->componentwise != 0 && p->componentwise != 1) return fail(DFW_EINVAL, "componentwise must be 0 or 1");
+  if (p->df_stage != 0 && p->df_stage != 1) return fail(DFW_EINVAL, "df_stage must be 0 or 1");
   if (dtype != DFW_F64 && dtype != DFW_F32) return fail(DFW_EDTYPE, "dtype must be DFW_F64 or DFW_F32");
   return DFW_OK;
 }
@@ -794,6 +812,8 @@ static Scheme make_scheme(const dfw_params* p) {
   S.ts = p->time_scheme;
   S.t_end = p->t_end;
   S.sw = p->switch_rule;
+  S.cw = p->componentwise;
+  S.dfs = p->df_stage;
   return S;
 }
 
@@ -852,7 +872,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
     for (int n = 0; n < nsteps; ++n) {
       before_step(n);
       L.step = n;
-      L.out = OUT_F;
+      L.out = OUT_F | (S.dfs ? OUT_DF : 0);
       L.lead = 1;
       L.dt_host = dt_first;
       L.dt_hist = dt_hist;
@@ -861,6 +881,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
         hipLaunchKernelGGL((k_rk_stage<real, 1>), dim3(nb), dim3(kCellBlock), 0, st, W, (const real*)nullptr, FX, FY,
                            Ws, ctrls, G0, grids, cblocks, n);
       });
+      L.out = OUT_F;
       L.lead = 0;
       L.dt_host = 0.0;
       L.dt_hist = nullptr;
@@ -869,7 +890,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
         hipLaunchKernelGGL((k_rk_stage<real, 2>), dim3(nb), dim3(kCellBlock), 0, st, W, Ws, FX, FY, R, ctrls, G0,
                            grids, cblocks, n);
       });
-      L.out = OUT_F | OUT_DF;
+      L.out = OUT_F | (S.dfs ? 0 : OUT_DF);
       timed(DFW_K_RK_FACES, st, [&] { launch_faces<real>(L, R, A, FX, FY, st); });
       timed(DFW_K_RK_UPDATE, st, [&] {
         hipLaunchKernelGGL(k_rk_final<real>, dim3(nb), dim3(kCellBlock), 0, st, W, A, R, FX, FY, ctrls, G0, grids,
@@ -881,7 +902,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
   for (int n = 0; n < nsteps; ++n) {
     before_step(n);
     L.step = n;
-    L.out = OUT_F | OUT_FT | (S.tl ? OUT_OMEGA : 0);
+    L.out = OUT_F | OUT_FT | (S.tl ? OUT_OMEGA : 0) | (S.dfs ? OUT_DF : 0);
     L.lead = 1;
     L.dt_host = dt_first;
     L.dt_hist = dt_hist;
@@ -890,7 +911,7 @@ static void enqueue_steps(real* W, real* A, real* Ws, real* R, real* FX, real* F
       hipLaunchKernelGGL(k_update1<real>, dim3(nb), dim3(kCellBlock), 0, st, W, FX, FY, Ws, R, ctrls, G0, grids,
                          cblocks, n, S.tl);
     });
-    L.out = OUT_FT | OUT_DF | (S.tl ? OUT_OMEGA : 0);
+    L.out = OUT_FT | (S.dfs ? 0 : OUT_DF) | (S.tl ? OUT_OMEGA : 0);
     L.lead = 0;
     L.dt_host = 0.0;
     L.dt_hist = nullptr;
@@ -1311,6 +1332,8 @@ dfw_status dfw_adjoint(const dfw_grid* grid, const dfw_params* params, int32_t d
   if (params->time_limiter) return fail(DFW_EINVAL, "the adjoint does not cover the time limiter");
   if (params->time_scheme != DFW_TIME_S2O4) return fail(DFW_EINVAL, "the adjoint covers the S2O4 step only");
   if (params->t_end > 0.0) return fail(DFW_EINVAL, "the adjoint takes its time steps from dt_hist; t_end must be 0");
+  if (params->componentwise || params->df_stage)
+    return fail(DFW_EINVAL, "the adjoint covers the characteristic reconstruction and the DF of the last stage");
   if (!gW_final || !gW0) return fail(DFW_EINVAL, "gW_final and gW0 must be non-null");
   if (!dt_hist_dev && nsteps > 0) return fail(DFW_EINVAL, "dt_hist_dev is required");
   if ((s = check_ckpt(grid, dtype, nsteps, ckpt_every, ckpt, ckpt_bytes)) != DFW_OK) return s;

@@ -35,18 +35,18 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "probe.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dfweno.h"\nint main(void){'
-                   'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dfw_grid), offsetof(dfw_grid, dx),'
+                   'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dfw_grid), offsetof(dfw_grid, dx),'
                    ' offsetof(dfw_grid, bc_y), sizeof(dfw_params), offsetof(dfw_params, c2),'
                    ' offsetof(dfw_params, tile), offsetof(dfw_params, time_limiter),'
                    ' offsetof(dfw_params, time_scheme), offsetof(dfw_params, t_end),'
-                   ' offsetof(dfw_params, switch_rule)); return 0;}\n')
+                   ' offsetof(dfw_params, switch_rule), offsetof(dfw_params, df_stage)); return 0;}\n')
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(_lib.dfw_grid), _lib.dfw_grid.dx.offset, _lib.dfw_grid.bc_y.offset,
             ctypes.sizeof(_lib.dfw_params), _lib.dfw_params.c2.offset, _lib.dfw_params.tile.offset,
             _lib.dfw_params.time_limiter.offset, _lib.dfw_params.time_scheme.offset, _lib.dfw_params.t_end.offset,
-            _lib.dfw_params.switch_rule.offset]
+            _lib.dfw_params.switch_rule.offset, _lib.dfw_params.df_stage.offset]
     assert out == want
 
 
@@ -56,7 +56,8 @@ def _grid(nx=8, ny=8):
 
 def _params(**kw):
     d = dict(gamma=1.4, cfl=0.5, dt_fixed=0.0, alpha_thres=0.5, d_h=0.85, d_l=0.85, eps_weno=1e-6, c1=0.01, c2=5.0,
-             flux=0, tile=0, time_limiter=0, time_scheme=0, t_end=0.0, switch_rule=0)
+             flux=0, tile=0, time_limiter=0, time_scheme=0, t_end=0.0, switch_rule=0, componentwise=0,
+             df_stage=0)
     d.update(kw)
     return _lib.dfw_params(*[d[k] for k, _ in _lib.dfw_params._fields_])
 
@@ -84,6 +85,8 @@ def test_workspace_bytes_host_only():
     (dict(params=_params(time_scheme=1, time_limiter=1)), _lib.DFW_EINVAL),
     (dict(params=_params(t_end=-1.0)), _lib.DFW_EINVAL),
     (dict(params=_params(switch_rule=3)), _lib.DFW_EINVAL),
+    (dict(params=_params(componentwise=2)), _lib.DFW_EINVAL),
+    (dict(params=_params(df_stage=-1)), _lib.DFW_EINVAL),
     (dict(dtype=5), _lib.DFW_EDTYPE),
     (dict(W=None), _lib.DFW_EINVAL),
     (dict(nsteps=-1), _lib.DFW_EINVAL),
@@ -128,6 +131,8 @@ def test_adjoint_validation_without_gpu():
     assert call(_params(time_limiter=1)) == _lib.DFW_EINVAL
     assert call(_params(time_scheme=1)) == _lib.DFW_EINVAL
     assert call(_params(t_end=0.5)) == _lib.DFW_EINVAL
+    assert call(_params(componentwise=1)) == _lib.DFW_EINVAL
+    assert call(_params(df_stage=1)) == _lib.DFW_EINVAL
     assert call(_params(), dt_hist=None) == _lib.DFW_EINVAL
     assert call(_params(), ckpt_bytes=ck - 1) == _lib.DFW_EINVAL
     assert L.dfw_run_ckpt(4096, 8192, ctypes.byref(g), ctypes.byref(_params()), n, 0, 0, 1 << 20, ck, 1 << 24,

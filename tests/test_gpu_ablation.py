@@ -1,0 +1,92 @@
+"""Ablation options on the GPU against the oracle, through the C ABI: component-wise reconstruction of
+the conservative variables (componentwise = 1; the characteristic reconstruction is the default)
+and alpha^{n+1} from the first stage's Gauss points (df_stage = 1; the last stage's is the default),
+for S2O4 with LF, GKS and the time limiter, SSP-RK3, single grids and the batched form."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2402_10914_amd import workloads as WL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2402_10914_amd import api
+    return api
+
+
+def _rel_l1(a, b):
+    if a.ndim == 2:
+        a, b = a[None], b[None]
+    return max(float(np.abs(a[c] - b[c]).sum() / max(np.abs(b[c]).sum(), 1e-300)) for c in range(a.shape[0]))
+
+
+def _pair(pr, nsteps, alpha=None, **kw):
+    api = _api()
+    alpha = pr.alpha if alpha is None else alpha
+    st = api.Stepper.for_problem(pr, api.Params(**kw), torch.float64)
+    W = torch.tensor(pr.W, device="cuda")
+    A = torch.tensor(alpha, device="cuda")
+    dth = torch.zeros(max(nsteps, 1), dtype=torch.float64, device="cuda")
+    t, fs = st.run(W, A, nsteps, dt_hist=dth)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    Wo, Ao, to, dto, fso = O.run(pr.W, alpha, g, O.make_params(**kw), nsteps)
+    return (W.cpu().numpy(), A.cpu().numpy(), dth.cpu().numpy()[:nsteps], fs), (Wo, Ao, dto, fso)
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_componentwise_rhs_parity(flux):
+    api = _api()
+    pr = WL.riemann4(37, 23, seed=5)
+    alpha = np.random.default_rng(8).uniform(0.2, 1.0, (23, 37))
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    dt = 0.4 / O.max_speed(pr.W, g, O.make_params())[0]
+    Lo, Lto, ao = O.rhs(pr.W, alpha, g, O.make_params(flux=flux, componentwise=1), dt, want_alpha=True)
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, componentwise=1), torch.float64)
+    L, Lt, an = st.rhs(torch.tensor(pr.W, device="cuda"), torch.tensor(alpha, device="cuda"), dt, want_alpha=True)
+    L, Lt, an = L.cpu().numpy(), Lt.cpu().numpy(), an.cpu().numpy()
+    assert _rel_l1(L, Lo) <= 1e-12
+    assert np.abs(Lt - Lto).sum() * dt <= 1e-12 * np.abs(Lo).sum()
+    assert _rel_l1(an, ao) <= 1e-12
+    Lc = O.rhs(pr.W, alpha, g, O.make_params(flux=flux), dt)[0]
+    assert _rel_l1(L, Lc) > 1e-6  # differs from the characteristic reconstruction
+
+
+@pytest.mark.parametrize("kw,nsteps", [(dict(flux=0), 15), (dict(flux=1), 15), (dict(flux=1, time_limiter=1), 4),
+                                       (dict(flux=0, time_scheme=1), 15)])
+@pytest.mark.parametrize("abl", [dict(componentwise=1), dict(df_stage=1), dict(componentwise=1, df_stage=1)])
+def test_ablation_runs_match_oracle(kw, nsteps, abl):
+    pr = WL.riemann4(40, 33, seed=12)
+    alpha = np.random.default_rng(13).uniform(0.2, 1.0, (33, 40))
+    (W, A, dth, fs), (Wo, Ao, dto, fso) = _pair(pr, nsteps, alpha=alpha, cfl=0.4, **kw, **abl)
+    assert fs == -1 and fso == -1
+    assert _rel_l1(W, Wo) <= 1e-12
+    assert _rel_l1(A, Ao) <= 1e-12
+    np.testing.assert_allclose(dth, dto, rtol=1e-12)
+
+
+def test_ablation_fp32_and_batch():
+    api = _api()
+    pr = WL.riemann4(40, 36, seed=36)
+    P = dict(flux=1, cfl=0.4, componentwise=1, df_stage=1)
+    st = api.Stepper.for_problem(pr, api.Params(**P), torch.float32)
+    W = torch.tensor(pr.W, dtype=torch.float32, device="cuda")
+    A = torch.tensor(pr.alpha, dtype=torch.float32, device="cuda")
+    _, fs = st.run(W, A, 6)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    Wo = O.run(pr.W, pr.alpha, g, O.make_params(**P), 6)[0]
+    assert fs == -1 and _rel_l1(W.double().cpu().numpy(), Wo) <= 1e-5
+    rng = np.random.default_rng(9)
+    probs = [WL.riemann4(int(a), int(b), seed=[9, k]) for k, (a, b) in enumerate(rng.integers(8, 50, (5, 2)))]
+    params = api.Params(**P)
+    b = api.Batch([(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y) for p in probs], params, torch.float64, 0)
+    Wb, Ab = b.pack([p.W for p in probs], [p.alpha for p in probs])
+    _, fsb = b.run(Wb, Ab, 5, use_graph=True)
+    for p, (w, a), f in zip(probs, b.unpack(Wb, Ab), fsb):
+        stp = api.Stepper.for_problem(p, params, torch.float64)
+        Wl = torch.tensor(p.W, device="cuda")
+        Al = torch.tensor(p.alpha, device="cuda")
+        _, fl = stp.run(Wl, Al, 5)
+        assert f == fl and torch.equal(w, Wl) and torch.equal(a, Al)
