@@ -44,7 +44,7 @@ enum { DFW_F64 = 0, DFW_F32 = 1 };
 enum { DFW_TIME_S2O4 = 0, DFW_TIME_SSPRK3 = 1 };  /* eq. (21) (Section 2.2), eq. (32) (Section 2.3) */
 
 /* Uniform structured grid: nx by ny cells of size dx by dy; one boundary type per axis.
- * Transmissive = ghost cells copy the nearest interior cell ("free" boundary of the paper). */
+ * Transmissive = ghost cells copy the nearest interior cell (the free boundary of Section 4). */
 typedef struct {
   int32_t nx, ny;
   double dx, dy;

@@ -700,7 +700,7 @@ static T df_gauss_point(const T* Wl, const T* Wr, double gamma) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Ghost arrays (Algorithm 1: "update boundary condition"); widths 3 (W) and 2 (alpha).        */
+/* Ghost arrays (the boundary-condition step of Algorithm 1); widths 3 (W) and 2 (alpha).     */
 /* ------------------------------------------------------------------------------------------ */
 constexpr int GW = 3, GA = 2;
 

@@ -31,15 +31,16 @@ RECONS = ("weno_ao", "hybrid", "hybrid_min", "hybrid_own")
 ALPHA0 = ("one", "initial")
 
 
-def solver_params(solver: str, recon: str, t_end: float = 0.0):
+def solver_params(solver: str, recon: str, t_end: float = 0.0, **ablation):
+    """Parameters of one configuration; `ablation` passes further options (componentwise, df_stage)."""
     from .api import FLUX_GKS, FLUX_LF, TIME_S2O4, TIME_SSPRK3, Params
     thres, rule = {"hybrid": (0.5, 0), "hybrid_min": (0.5, 1), "hybrid_own": (0.5, 2), "weno_ao": (0.0, 0)}[recon]
     if solver == "gks":
         return Params(flux=FLUX_GKS, cfl=0.5, alpha_thres=thres, switch_rule=rule, time_limiter=1,
-                      time_scheme=TIME_S2O4, t_end=t_end)
+                      time_scheme=TIME_S2O4, t_end=t_end, **ablation)
     if solver == "lf":
         return Params(flux=FLUX_LF, cfl=0.5, alpha_thres=thres, switch_rule=rule, time_scheme=TIME_SSPRK3,
-                      t_end=t_end)
+                      t_end=t_end, **ablation)
     raise ValueError(f"unknown solver {solver!r}")
 
 
@@ -74,7 +75,8 @@ def step_cap(pr) -> int:
     return int(math.ceil(4.0 * t_end / dt0)) + 20
 
 
-def survives(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None, alpha0: str = "one"):
+def survives(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None, alpha0: str = "one",
+             ablation: dict | None = None):
     """Runs the problem at every Mach number of `machs` as one batch; returns [bool] (survived)."""
     import torch
     from .api import Batch
@@ -82,7 +84,7 @@ def survives(problem: str, machs, solver: str, recon: str, n: int | None = None,
     make = WL.ROBUSTNESS[problem]
     probs = [make(float(m)) if n is None else make(float(m), n=n) for m in machs]
     t_end = probs[0].extra.get("t_end", 0.0)
-    params = solver_params(solver, recon, t_end)
+    params = solver_params(solver, recon, t_end, **(ablation or {}))
     if alpha0 == "initial":
         for p in probs:
             p.alpha = initial_alpha(p, params, dtype)
@@ -144,14 +146,19 @@ def main(argv=None) -> int:
     ap.add_argument("--rtol", type=float, default=0.01)
     ap.add_argument("--lo", type=float, default=1.0)
     ap.add_argument("--hi", type=float, default=200.0)
+    ap.add_argument("--componentwise", type=int, default=0, help="1: component-wise reconstruction (ablation)")
+    ap.add_argument("--df-stage", type=int, default=0, help="1: DF from the first stage (ablation)")
     a = ap.parse_args(argv)
+    ablation = dict(componentwise=a.componentwise, df_stage=a.df_stage)
     for prob in a.problems.split(","):
         for solver in a.solvers.split(","):
             for recon in a.recons.split(","):
                 for alpha0 in (a.alpha0.split(",") if recon != "weno_ao" else ["one"]):
                     t0 = time.time()
-                    r = max_mach(prob, solver, recon, lo=a.lo, hi=a.hi, k=a.k, rtol=a.rtol, alpha0=alpha0)
+                    r = max_mach(prob, solver, recon, lo=a.lo, hi=a.hi, k=a.k, rtol=a.rtol, alpha0=alpha0,
+                                 ablation=ablation)
                     r["alpha0"] = alpha0
+                    r.update(ablation)
                     r["seconds"] = round(time.time() - t0, 2)
                     print(json.dumps(r), flush=True)
     return 0
