@@ -7,7 +7,9 @@
   sampled patches (the oracle computes dt from the whole grid; each patch carries a 10-cell halo,
   of which one step contaminates at most 6), five steps with a fixed dt on patches with a 36-cell
   halo, and the full 50-step run checked by properties that hold at any size (no non-physical
-  state, conservation on the periodic grid, DF in [0, 1])."""
+  state, conservation on the periodic grid, DF in [0, 1]).
+* 512x512 Riemann with the paper's own solver configurations (GKS with the time limiter; SSP-RK3
+  with LF): the first steps against the oracle on the full grid."""
 import functools
 import os
 
@@ -175,3 +177,24 @@ def test_circles4096_fifty_steps_properties(flux, dtype):
     assert float(((s1 - s0).abs() / scale).max()) <= tol
     assert float(A.min()) >= 0.0 and float(A.max()) <= 1.0
     assert float(A.min()) < 0.5  # the blast edges engage the hybrid switch
+
+
+@pytest.mark.parametrize("kw,nsteps", [(dict(flux=WL.FLUX_GKS, time_limiter=1), 2),
+                                       (dict(flux=WL.FLUX_LF, time_scheme=1), 3)])
+def test_riemann512_paper_solver_configurations_full_grid(kw, nsteps):
+    """The paper's own solver configurations on the full 512x512 Riemann grid: S2O4 GKS with the time
+    limiter (two steps; the limited map amplifies rounding over longer runs) and SSP-RK3 with LF
+    (three steps), every cell against the oracle."""
+    pr = WL.riemann4(512, seed=2402)
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(cfl=0.4, **kw))
+    W = torch.tensor(pr.W, device="cuda")
+    A = torch.tensor(pr.alpha, device="cuda")
+    dth = torch.zeros(nsteps, dtype=torch.float64, device="cuda")
+    t, fs = st.run(W, A, nsteps, dt_hist=dth)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    Wo, Ao, to, dto, fso = O.run(pr.W, pr.alpha, g, O.make_params(cfl=0.4, **kw), nsteps)
+    assert fs == -1 and fso == -1
+    assert _rel_l1_rows(W.cpu().numpy(), Wo) <= 1e-12
+    assert np.abs(A.cpu().numpy() - Ao).sum() / np.abs(Ao).sum() <= 1e-12
+    np.testing.assert_allclose(dth.cpu().numpy(), dto, rtol=1e-12)
