@@ -37,7 +37,11 @@ def _arch() -> str:
 
 
 def _key(kind, sizes, dtype, params: api.Params) -> str:
-    h = hashlib.sha1(json.dumps(sorted(sizes)).encode()).hexdigest()[:12]
+    """Problem sizes, every scheme option but the tile itself, and the library's tile shapes (a
+    tile index means another shape in a library with another shape list)."""
+    opts = {k: v for k, v in sorted(params.__dict__.items()) if k != "tile"}
+    blob = json.dumps([sorted(sizes), opts, api.tile_shapes()])
+    h = hashlib.sha1(blob.encode()).hexdigest()[:12]
     return f"{kind}|{_arch()}|hip{torch.version.hip}|{str(dtype).split('.')[-1]}|flux{params.flux}|{h}"
 
 

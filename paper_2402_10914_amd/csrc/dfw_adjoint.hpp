@@ -209,7 +209,7 @@ DFW_HD void unproject_adj_B_comp(const Basis<real>& B, real qc, const real* lw, 
 // gives, up to rounding: the reverse divides once per smoothness indicator and reuses the
 // reciprocals).
 // ------------------------------------------------------------------------------------------------
-template <class real, int NDEG>
+template <class real, int NDEG, int RULE = -1>
 DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, const real* lP, real* lQ,
                            real& la_c, real* P = nullptr) {
   const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
@@ -220,7 +220,7 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
   real lP0 = lP[0], lP1 = NDEG > 1 ? lP[1] : real(0), lP2 = NDEG > 2 ? lP[2] : real(0);
   real lP3 = NDEG > 3 ? lP[3] : real(0), lP4 = NDEG > 4 ? lP[4] : real(0);
   real l10, l11, l12;  // adjoints of p1's coefficients
-  if (df_switch(a_lo, a_c, a_hi, k)) {
+  if (df_switch<RULE>(a_lo, a_c, a_hi, k)) {
     la_c += lP0 * (p1_0 - Q2) + lP1 * p1_1 + lP2 * p1_2;
     lQ[2] += lP0 * (real(1) - a_c);
     if (P) {
@@ -1020,7 +1020,7 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
 // side (side 0: cells f-3..f+1; side 1: cells f+2..f-2); (a_lo, a_c, a_hi) the DF of the stencil's
 // cells 1..3 in the same order; sgn_inv_dn = +1/dn (side 0) or -1/dn (side 1).  Gives the line
 // value w and its normal derivative wn.
-template <class real>
+template <int RULE = -1, class real>
 DFW_HD void normal_side(const Basis<real>& B, const real (*cs)[4], real a_lo, real a_c, real a_hi, real sgn_inv_dn,
                         const Coef<real>& k, real* w, real* wn) {
   real Q[5][4];
@@ -1032,7 +1032,7 @@ DFW_HD void normal_side(const Basis<real>& B, const real (*cs)[4], real a_lo, re
     real s[5], P2[2];
 #pragma unroll
     for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-    recon_poly<real, 2>(s, a_lo, a_c, a_hi, k, P2);
+    recon_poly<real, 2, RULE>(s, a_lo, a_c, a_hi, k, P2);
     q[c] = P2[0];
     qd[c] = P2[1] * sgn_inv_dn;
   }
@@ -1044,7 +1044,7 @@ DFW_HD void normal_side(const Basis<real>& B, const real (*cs)[4], real a_lo, re
 // adjoints go to lc_add(m, c, v) (add v to cell m, component c); the basis adjoint lB and la_c (the
 // DF of the reconstructed cell, DF branch only) accumulate.  One characteristic component at a time: its projection, reconstruction forward and
 // backward, and its share of the projection adjoints, so that only one chain is live.
-template <int C, class real, class CellFn, class AddFn>
+template <int C, int RULE, class real, class CellFn, class AddFn>
 DFW_HD void normal_side_adj_comp(const Basis<real>& B, CellFn cell, real a_lo, real a_c, real a_hi, real sgn_inv_dn,
                                  const Coef<real>& k, const real* lw, const real* lwn, real lqc, real lqdc,
                                  AddFn lc_add, BasisAdj<real>& lB, real& la_c) {
@@ -1058,7 +1058,7 @@ DFW_HD void normal_side_adj_comp(const Basis<real>& B, CellFn cell, real a_lo, r
   }
   lP[0] = lqc;
   lP[1] = lqdc * sgn_inv_dn;
-  recon_poly_adj<real, 2>(s, a_lo, a_c, a_hi, k, lP, lQc, la_c, P2);
+  recon_poly_adj<real, 2, RULE>(s, a_lo, a_c, a_hi, k, lP, lQc, la_c, P2);
   unproject_adj_B_comp<C>(B, P2[0], lw, lB);
   unproject_adj_B_comp<C>(B, P2[1] * sgn_inv_dn, lwn, lB);
 #pragma unroll
@@ -1075,24 +1075,24 @@ DFW_HD void normal_side_adj_comp(const Basis<real>& B, CellFn cell, real a_lo, r
 
 // cell(m, c) is read once per component; callers that keep the cells in memory pass a reader that
 // reloads them, so that nothing but the accumulators lives from one component to the next.
-template <class real, class CellFn, class AddFn>
+template <int RULE = -1, class real, class CellFn, class AddFn>
 DFW_HD void normal_side_adj(const Basis<real>& B, CellFn cell, real a_lo, real a_c, real a_hi, real sgn_inv_dn,
                             const Coef<real>& k, const real* lw, const real* lwn, AddFn lc_add, BasisAdj<real>& lB,
                             real& la_c) {
-  normal_side_adj_comp<0>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<0>(B, lw),
+  normal_side_adj_comp<0, RULE>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<0>(B, lw),
                           unproject_adj_q_comp<0>(B, lwn), lc_add, lB, la_c);
-  normal_side_adj_comp<1>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<1>(B, lw),
+  normal_side_adj_comp<1, RULE>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<1>(B, lw),
                           unproject_adj_q_comp<1>(B, lwn), lc_add, lB, la_c);
-  normal_side_adj_comp<2>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<2>(B, lw),
+  normal_side_adj_comp<2, RULE>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<2>(B, lw),
                           unproject_adj_q_comp<2>(B, lwn), lc_add, lB, la_c);
-  normal_side_adj_comp<3>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<3>(B, lw),
+  normal_side_adj_comp<3, RULE>(B, cell, a_lo, a_c, a_hi, sgn_inv_dn, k, lw, lwn, unproject_adj_q_comp<3>(B, lw),
                           unproject_adj_q_comp<3>(B, lwn), lc_add, lB, la_c);
 }
 
 // Segment, one side: line(m, c) = component c of the side's line value on segment row m-2;
 // al = DF of the side's cell on rows -1, 0, +1.  Gives the states and their tangential derivatives
 // at the two Gauss points (as segment_fluxes computes them).
-template <class real, class LineFn>
+template <int RULE = -1, class real, class LineFn>
 DFW_HD void segment_side(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
                          real (*gw)[4], real (*gwt)[4]) {
   real Q[5][4];
@@ -1109,7 +1109,7 @@ DFW_HD void segment_side(const Basis<real>& B, LineFn line, const real* al, real
     real s[5], Pc[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-    recon_poly<real, 5>(s, al[0], al[1], al[2], k, Pc);
+    recon_poly<real, 5, RULE>(s, al[0], al[1], al[2], k, Pc);
     real v0, d0, v1, d1;
     eval_poly_at(Pc, real(kXiGp0), v0, d0);
     eval_poly_at(Pc, real(kXiGp1), v1, d1);
@@ -1128,7 +1128,7 @@ DFW_HD void segment_side(const Basis<real>& B, LineFn line, const real* al, real
 // Reverse of segment_side for the adjoints lgw, lgwt of the Gauss-point states: the adjoints of the
 // side's line values go to ll_add(m, c, v); lB and la_c accumulate.  One characteristic component at a time, as in
 // normal_side_adj.
-template <int C, class real, class LineFn, class AddFn>
+template <int C, int RULE, class real, class LineFn, class AddFn>
 DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
                                   const real (*lgw)[4], const real (*lgwt)[4], real lqv0, real lqv1, real lqd0,
                                   real lqd1, AddFn ll_add, BasisAdj<real>& lB, real& la_c) {
@@ -1142,7 +1142,7 @@ DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real*
   }
   eval_poly_at_adj(real(kXiGp0), lqv0, lqd0 * inv_dt, lP);
   eval_poly_at_adj(real(kXiGp1), lqv1, lqd1 * inv_dt, lP);
-  recon_poly_adj<real, 5>(s, al[0], al[1], al[2], k, lP, lQc, la_c, Pc);
+  recon_poly_adj<real, 5, RULE>(s, al[0], al[1], al[2], k, lP, lQc, la_c, Pc);
   real v0, d0, v1, d1;
   eval_poly_at(Pc, real(kXiGp0), v0, d0);
   eval_poly_at(Pc, real(kXiGp1), v1, d1);
@@ -1162,12 +1162,12 @@ DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real*
   }
 }
 
-template <class real, class LineFn, class AddFn>
+template <int RULE = -1, class real, class LineFn, class AddFn>
 DFW_HD void segment_side_adj(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
                              const real (*lgw)[4], const real (*lgwt)[4], AddFn ll_add, BasisAdj<real>& lB,
                              real& la_c) {
 #define DFW_SEG_COMP(C)                                                                                          \
-  segment_side_adj_comp<C>(B, line, al, inv_dt, k, lgw, lgwt, unproject_adj_q_comp<C>(B, lgw[0]),              \
+  segment_side_adj_comp<C, RULE>(B, line, al, inv_dt, k, lgw, lgwt, unproject_adj_q_comp<C>(B, lgw[0]),        \
                            unproject_adj_q_comp<C>(B, lgw[1]), unproject_adj_q_comp<C>(B, lgwt[0]),            \
                            unproject_adj_q_comp<C>(B, lgwt[1]), ll_add, lB, la_c)
   DFW_SEG_COMP(0);

@@ -27,13 +27,16 @@ struct Coef {
 // Eq. (42): the DF quadratic replaces WENO-AO for a cell when the largest DF value of the cell and
 // its two neighbours along the sweep is below the threshold (strict).  Readings kept as options:
 // sw_rule 1 takes the smallest of the three (a discontinuity in any of them), 2 the cell's own value.
-template <class real>
+// RULE >= 0 fixes the rule at compile time (for kernels at the register limit, where a rule read at
+// run time costs spills); RULE < 0 reads k.sw_rule.
+template <int RULE = -1, class real>
 DFW_HD inline bool df_switch(real a_lo, real a_c, real a_hi, const Coef<real>& k) {
+  const int rule = RULE >= 0 ? RULE : k.sw_rule;
   real mx = a_lo > a_c ? a_lo : a_c;
   mx = mx > a_hi ? mx : a_hi;
   real mn = a_lo < a_c ? a_lo : a_c;
   mn = mn < a_hi ? mn : a_hi;
-  const real a = k.sw_rule == 1 ? mn : (k.sw_rule == 2 ? a_c : mx);
+  const real a = rule == 1 ? mn : (rule == 2 ? a_c : mx);
   return a < k.alpha_thres;
 }
 
@@ -158,14 +161,14 @@ DFW_HD void weno_indicators(const real* Q, real* b) {
 }
 
 // ------------------------------------------------------------------------------------------------
-template <class real, int NDEG>
+template <class real, int NDEG, int RULE = -1>
 DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, real* P) {
   const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
   // candidate p1 (centred quadratic): coefficients of 1, xi, xi^2
   real p1_0 = (real(5) * Q2 + real(2) * Q3 - Q1) * real(1.0 / 6.0);
   real p1_1 = Q3 - Q2;
   real p1_2 = real(0.5) * (Q1 + Q3) - Q2;
-  if (df_switch(a_lo, a_c, a_hi, k)) {
+  if (df_switch<RULE>(a_lo, a_c, a_hi, k)) {
     P[0] = Q2 + a_c * (p1_0 - Q2);
     if (NDEG > 1) P[1] = a_c * p1_1;
     if (NDEG > 2) P[2] = a_c * p1_2;

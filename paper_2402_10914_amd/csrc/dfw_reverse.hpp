@@ -44,7 +44,9 @@ __device__ __forceinline__ real pair_swap(real x) {
 // STAGE 2: seeds lam_Lt = dt^2/3 P (P = adjoint of W^{n+1}) and the adjoint LA of alpha^{n+1}, with
 //          the stage's interface DF products DX, DY.
 // Thread 2p + s works on side s of interface segment p (s = 0: the cell before the interface).
-template <class real, int FLUX, int STAGE, int TF, int TR>
+// RULE >= 0 fixes the hybrid switch rule at compile time (its selects fold away: this kernel is at
+// the register limit and pays for every live value); RULE < 0 reads the rule of S at run time.
+template <class real, int FLUX, int STAGE, int TF, int TR, int RULE>
 __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
     const real* __restrict__ W, const real* __restrict__ alpha, const real* __restrict__ P,
     const real* __restrict__ Q, const real* __restrict__ LA, const real* __restrict__ DX,
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
   const real dt = real(dt_hist[step]);
-  const Coef<real> k = make_coef<real>(S);
+  const Coef<real> k = make_coef<real, RULE>(S);
 
   // ---- stage cells (rows t0-4 .. t0+TR+3) and alpha in LDS, local component order
   for (int e = tid; e < T::NQ * T::WN; e += T::NT) {
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
     const Basis<real> B = basis_row(q);
     real cs[5][4], w[4];
     stencil(q, cs);
-    normal_side<real>(B, cs, a_of(q, 0), a_of(q, 1), a_of(q, 2), sgn_dn, k, w, dn);
+    normal_side<RULE>(B, cs, a_of(q, 0), a_of(q, 1), a_of(q, 2), sgn_dn, k, w, dn);
 #pragma unroll
     for (int c = 0; c < 4; ++c) sL[c][2 * lidx(q, fl) + side] = w[c];
   };
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   for (int g = 0; g < 2; ++g)
 #pragma unroll
     for (int c = 0; c < 4; ++c) gw[g][c] = gwt[g][c] = real(0);
-  if (seg) segment_side(B, line, al, inv_dt, k, gw, gwt);
+  if (seg) segment_side<RULE>(B, line, al, inv_dt, k, gw, gwt);
 
   // ---- adjoints of the face sums from the cell seeds (face f: -1/dn to cell f-1, +1/dn to cell f)
   const int cmap[4] = {0, dir ? 2 : 1, dir ? 1 : 2, 3};
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   real la_seg = real(0);
   if (seg) {
     auto ll_add = [&](int m, int c, real v) { ll[m][c] += v; };
-    segment_side_adj(B, line, al, inv_dt, k, lgw, lgwt, ll_add, lB, la_seg);
+    segment_side_adj<RULE>(B, line, al, inv_dt, k, lgw, lgwt, ll_add, lB, la_seg);
   }
   real acc[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   if (own) {
     auto cell = [&](int m, int c) -> real { return sW[c][rr + 2][fl + (side ? 5 - m : m)]; };
     auto lc_add = [&](int m, int c, real v) { lcs[m][c] += v; };
-    normal_side_adj<real>(B, cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc, lwn, lc_add, lB,
+    normal_side_adj<RULE>(B, cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc, lwn, lc_add, lB,
                           la_ns);
   }
   // basis adjoint of the pair (side 0 first on both lanes), then the two cells it is built from
@@ -497,9 +499,12 @@ static void launch_adj_faces(const real* W, const real* A, const real* P, const 
                              const real* DX, const real* DY, real* BX, real* BY, const GridDesc& G, const Scheme& S,
                              const double* dt_hist, int step, hipStream_t st) {
   constexpr int TF = kAdjShapes[FLUX].tf, TR = kAdjShapes[FLUX].tr;
-  hipLaunchKernelGGL((k_adj_faces<real, FLUX, STAGE, TF, TR>), dim3(adj_tiles(FLUX, G.nx, G.ny)),
-                     dim3(2 * TF * (TR + 4)),
-                     0, st, W, A, P, Q, LA, DX, DY, BX, BY, G, S, dt_hist, step);
+  if (S.sw == 0)  // the switch of eq. (42) as printed
+    hipLaunchKernelGGL((k_adj_faces<real, FLUX, STAGE, TF, TR, 0>), dim3(adj_tiles(FLUX, G.nx, G.ny)),
+                       dim3(2 * TF * (TR + 4)), 0, st, W, A, P, Q, LA, DX, DY, BX, BY, G, S, dt_hist, step);
+  else
+    hipLaunchKernelGGL((k_adj_faces<real, FLUX, STAGE, TF, TR, -1>), dim3(adj_tiles(FLUX, G.nx, G.ny)),
+                       dim3(2 * TF * (TR + 4)), 0, st, W, A, P, Q, LA, DX, DY, BX, BY, G, S, dt_hist, step);
 }
 
 // Checkpoint store: one slot per segment of ckpt_every steps, slot = W (4N) | alpha (N).

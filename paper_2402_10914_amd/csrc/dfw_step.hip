@@ -70,7 +70,8 @@ struct Scheme {
 enum { OUT_F = 1, OUT_FT = 2, OUT_DF = 4, OUT_OMEGA = 8 };
 constexpr int kFacePlanes = 10;  // F (4), dF/dt (4), DF product, time-limiter weight
 
-template <class real>
+// RULE >= 0 fixes the hybrid switch rule at compile time; RULE < 0 takes the rule of S.
+template <class real, int RULE = -1>
 __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
   Coef<real> k;
   k.gamma = real(S.gamma);
@@ -86,7 +87,7 @@ __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
   k.inv_d3 = real(1.0 / S.d[3]);
   k.K2 = real(S.K + 2.0);
   k.k4K2 = real(4.0 / (S.K + 2.0));
-  k.sw_rule = S.sw;
+  k.sw_rule = RULE >= 0 ? RULE : S.sw;
   return k;
 }
 
@@ -673,7 +674,7 @@ static void timed(int kind, hipStream_t st, Launch launch) {
 struct TileShape {
   int tf, tr;
 };
-static const TileShape kShapes[] = {{16, 28}, {8, 60}, {32, 12}, {16, 12}};
+static const TileShape kShapes[] = {{8, 28}, {16, 28}, {8, 60}, {16, 12}, {4, 60}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 static int shape_tiles(int shape, int nx, int ny) {
@@ -703,10 +704,11 @@ static void launch_faces_t(const FaceLaunch& L, const real* W, const real* A, re
 template <class real, int FLUX, int OUT>
 static void launch_faces_shape(const FaceLaunch& L, const real* W, const real* A, real* FX, real* FY, hipStream_t st) {
   switch (L.shape) {
-    case 1: launch_faces_t<real, FLUX, OUT, 8, 60>(L, W, A, FX, FY, st); break;
-    case 2: launch_faces_t<real, FLUX, OUT, 32, 12>(L, W, A, FX, FY, st); break;
+    case 1: launch_faces_t<real, FLUX, OUT, 16, 28>(L, W, A, FX, FY, st); break;
+    case 2: launch_faces_t<real, FLUX, OUT, 8, 60>(L, W, A, FX, FY, st); break;
     case 3: launch_faces_t<real, FLUX, OUT, 16, 12>(L, W, A, FX, FY, st); break;
-    default: launch_faces_t<real, FLUX, OUT, 16, 28>(L, W, A, FX, FY, st); break;
+    case 4: launch_faces_t<real, FLUX, OUT, 4, 60>(L, W, A, FX, FY, st); break;
+    default: launch_faces_t<real, FLUX, OUT, 8, 28>(L, W, A, FX, FY, st); break;
   }
 }
 

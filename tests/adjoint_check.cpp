@@ -208,8 +208,8 @@ int main() {
         auto c1 = [&](int m, int c) -> real { return cs1[m][c]; };
         auto add0 = [&](int m, int c, real v) { lcs0[m][c] += v; };
         auto add1 = [&](int m, int c, real v) { lcs1[m][c] += v; };
-        normal_side_adj<real>(B, c0, xx[24], xx[25], xx[26], idn, k, l, l + 8, add0, lB, la1);
-        normal_side_adj<real>(B, c1, xx[27], xx[26], xx[25], -idn, k, l + 4, l + 12, add1, lB, la2);
+        normal_side_adj(B, c0, xx[24], xx[25], xx[26], idn, k, l, l + 8, add0, lB, la1);
+        normal_side_adj(B, c1, xx[27], xx[26], xx[25], -idn, k, l + 4, l + 12, add1, lB, la2);
         for (int m = 0; m < 5; ++m)
           for (int c = 0; c < 4; ++c) {
             lx[4 * m + c] += lcs0[m][c];
@@ -232,8 +232,8 @@ int main() {
           }
         normal_sweep<real>(cell, x[24], x[25], x[26], x[27], idn, k, y, y + 4, y + 8, y + 12);
         Basis<real> B = make_basis(cell[2], cell[3], k);
-        normal_side<real>(B, cs0, x[24], x[25], x[26], idn, k, w, w + 8);
-        normal_side<real>(B, cs1, x[27], x[26], x[25], -idn, k, w + 4, w + 12);
+        normal_side(B, cs0, x[24], x[25], x[26], idn, k, w, w + 8);
+        normal_side(B, cs1, x[27], x[26], x[25], -idn, k, w + 4, w + 12);
         double d = 0;
         for (int i = 0; i < 16; ++i) d = std::max(d, std::fabs(w[i] - y[i]) / (std::fabs(y[i]) + 1e-300));
         std::printf("%s %.3e\n", branch ? "normal_side_fwd_df" : "normal_side_fwd", d);
