@@ -30,7 +30,7 @@ struct Coef {
 // RULE >= 0 fixes the rule at compile time (for kernels at the register limit, where a rule read at
 // run time costs spills); RULE < 0 reads k.sw_rule.
 template <int RULE = -1, class real>
-DFW_HD inline bool df_switch(real a_lo, real a_c, real a_hi, const Coef<real>& k) {
+DFW_HD bool df_switch(real a_lo, real a_c, real a_hi, const Coef<real>& k) {
   const int rule = RULE >= 0 ? RULE : k.sw_rule;
   real mx = a_lo > a_c ? a_lo : a_c;
   mx = mx > a_hi ? mx : a_hi;
