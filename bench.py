@@ -220,7 +220,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the step is benchmarked on one MI355X); "
+        print("bench.py measures the step on a single MI355X (the library has no multi-GPU path); "
               f"--gpus {args.gpus} / WORLD_SIZE {world} is not supported.", file=sys.stderr)
         sys.exit(2)
     if args.mode == "copy":
