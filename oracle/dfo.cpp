@@ -29,7 +29,12 @@
  *   (R24) second-stage GKS integrals use the same dt and tau_n formula as the first stage.
  *   (R29) SSP-RK3 (eq. (32)): dt from the CFL condition on W^n, alpha^n in all three stages,
  *        alpha^{n+1} from the Gauss-point states of the third stage.
- * Functions that are not pinned by a closed form, a special case or brute force say so.
+ * Functions that are not pinned by a closed form, a special case or brute force say so.  Every
+ * function's arithmetic has such a pin; the following readings are choices the paper leaves open
+ * and no value it prints can decide, so they are parity unpinned (the tests pin only that the
+ * code follows the stated choice): which stage's Gauss points feed alpha^{n+1} (R5; R29 for
+ * SSP-RK3), the normal derivative at the Gauss points (R9), and the sub-stencils and components
+ * over which the time-limiter weight takes beta_min, beta_max and its minimum (R28).
  */
 #include <algorithm>
 #include <cmath>
