@@ -161,8 +161,34 @@ DFW_HD void weno_indicators(const real* Q, real* b) {
 }
 
 // ------------------------------------------------------------------------------------------------
+// Non-linear time limiter (Section 2.2, eqs. (27)-(29)).  Weight of one reconstruction:
+//   a1 = 1 + (tau_Z / (beta_min + eps))^2,  a2 = 1 + (tau_Z / (beta_max + eps))^2,
+//   alpha = 2 a2 / (a1 + a2)  (in (0, 1]: 1 on smooth data, -> 0 across a jump),
+// beta_min, beta_max over the four indicators of eq. (38), tau_Z of eq. (37).  The weight of an
+// interface is the smallest over the characteristic components of the two normal reconstructions
+// beside it; recon_poly hands it out of the normal sweep (from the ratios tau/(beta_k + eps) that
+// its WENO-Z weights already hold, or from this function where the DF branch skips them).
+// ------------------------------------------------------------------------------------------------
+template <class real>
+DFW_HD real time_limiter_weight(const real* Q, const Coef<real>& k) {
+  real b[4];
+  weno_indicators(Q, b);
+  const real tau = (fabs(b[3] - b[0]) + fabs(b[3] - b[1]) + fabs(b[3] - b[2])) * real(1.0 / 3.0);
+  real bmin = b[0] < b[1] ? b[0] : b[1], bmax = b[0] > b[1] ? b[0] : b[1];
+  bmin = bmin < b[2] ? bmin : b[2];
+  bmin = bmin < b[3] ? bmin : b[3];
+  bmax = bmax > b[2] ? bmax : b[2];
+  bmax = bmax > b[3] ? bmax : b[3];
+  const real x1 = tau / (bmin + k.eps), x2 = tau / (bmax + k.eps);
+  const real a1 = real(1) + x1 * x1, a2 = real(1) + x2 * x2;
+  return real(2) * a2 / (a1 + a2);
+}
+
+// ------------------------------------------------------------------------------------------------
+// With om non-null it also stores the time-limiter weight of this stencil (eq. (29)).
 template <class real, int NDEG, int RULE = -1>
-DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, real* P) {
+DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, real* P,
+                       real* om = nullptr) {
   const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
   // candidate p1 (centred quadratic): coefficients of 1, xi, xi^2
   real p1_0 = (real(5) * Q2 + real(2) * Q3 - Q1) * real(1.0 / 6.0);
@@ -174,6 +200,7 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
     if (NDEG > 2) P[2] = a_c * p1_2;
     if (NDEG > 3) P[3] = real(0);
     if (NDEG > 4) P[4] = real(0);
+    if (om) *om = time_limiter_weight(Q, k);
     return;
   }
   real p0_0 = (real(2) * Q0 - real(7) * Q1 + real(11) * Q2) * real(1.0 / 6.0);
@@ -196,6 +223,15 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
   const real i01 = real(1) / (B0 * B1), i23 = real(1) / (B2 * B3);
   real r0 = tau * (B1 * i01), r1 = tau * (B0 * i01), r2 = tau * (B3 * i23), r3 = tau * (B2 * i23);
+  if (om) {  // tau/(beta_min + eps) and tau/(beta_max + eps) are the largest and smallest ratio
+    real rmax = r0 > r1 ? r0 : r1, rmin = r0 < r1 ? r0 : r1;
+    rmax = rmax > r2 ? rmax : r2;
+    rmax = rmax > r3 ? rmax : r3;
+    rmin = rmin < r2 ? rmin : r2;
+    rmin = rmin < r3 ? rmin : r3;
+    const real a1 = real(1) + rmax * rmax, a2 = real(1) + rmin * rmin;
+    *om = real(2) * a2 / (a1 + a2);
+  }
   real w0 = k.d[0] * (real(1) + r0 * r0);
   real w1 = k.d[1] * (real(1) + r1 * r1);
   real w2 = k.d[2] * (real(1) + r2 * r2);
@@ -223,50 +259,6 @@ DFW_HD void eval_poly_at(const real* P, real xi, real& val, real& der) {
   der = ((real(4) * P[4] * xi + real(3) * P[3]) * xi + real(2) * P[2]) * xi + P[1];
 }
 
-// ------------------------------------------------------------------------------------------------
-// Non-linear time limiter (Section 2.2, eqs. (27)-(29)).  Weight of one reconstruction:
-//   a1 = 1 + (tau_Z / (beta_min + eps))^2,  a2 = 1 + (tau_Z / (beta_max + eps))^2,
-//   alpha = 2 a2 / (a1 + a2)  (in (0, 1]: 1 on smooth data, -> 0 across a jump),
-// beta_min, beta_max over the four indicators of eq. (38), tau_Z of eq. (37).
-// ------------------------------------------------------------------------------------------------
-template <class real>
-DFW_HD real time_limiter_weight(const real* Q, const Coef<real>& k) {
-  real b[4];
-  weno_indicators(Q, b);
-  const real tau = (fabs(b[3] - b[0]) + fabs(b[3] - b[1]) + fabs(b[3] - b[2])) * real(1.0 / 3.0);
-  real bmin = b[0] < b[1] ? b[0] : b[1], bmax = b[0] > b[1] ? b[0] : b[1];
-  bmin = bmin < b[2] ? bmin : b[2];
-  bmin = bmin < b[3] ? bmin : b[3];
-  bmax = bmax > b[2] ? bmax : b[2];
-  bmax = bmax > b[3] ? bmax : b[3];
-  const real x1 = tau / (bmin + k.eps), x2 = tau / (bmax + k.eps);
-  const real a1 = real(1) + x1 * x1, a2 = real(1) + x2 * x2;
-  return real(2) * a2 / (a1 + a2);
-}
-
-// Weight omega of an interface: the smallest weight over the characteristic components of the two
-// normal reconstructions beside it (cells 2 and 3 of its six-cell row, each with its own stencil).
-template <class real, bool CHAR = true>
-DFW_HD real time_limiter_omega(const real (*cell)[4], const Coef<real>& k) {
-  const Basis<real> B = recon_basis<CHAR>(cell[2], cell[3], k);
-  real Q[6][4];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) to_recon<CHAR>(B, cell[m], Q[m]);
-  real om = real(1);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    real sl[5], sr[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      sl[m] = Q[m][c];
-      sr[m] = Q[m + 1][c];
-    }
-    const real wl = time_limiter_weight(sl, k), wr = time_limiter_weight(sr, k);
-    om = om < wl ? om : wl;
-    om = om < wr ? om : wr;
-  }
-  return om;
-}
 
 // ------------------------------------------------------------------------------------------------
 // Primitive variables and the DF of one Gauss point (Section 3.2):
@@ -551,23 +543,26 @@ DFW_HD void gks_flux(const real* wl, const real* wln, const real* wlt, const rea
 // ------------------------------------------------------------------------------------------------
 template <class real, bool CHAR = true>
 DFW_HD void normal_sweep(const real (*cell)[4], real a0, real a1, real a2, real a3, real inv_dn,
-                         const Coef<real>& k, real* wl, real* wr, real* wln, real* wrn) {
+                         const Coef<real>& k, real* wl, real* wr, real* wln, real* wrn, real* om = nullptr) {
   const Basis<real> B = recon_basis<CHAR>(cell[2], cell[3], k);
   real Q[6][4];
 #pragma unroll
   for (int m = 0; m < 6; ++m) to_recon<CHAR>(B, cell[m], Q[m]);
   real ql[4], qld[4], qr[4], qrd[4];
+  real omin = real(1), wk = real(1);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     real s[5], P2[2];
 #pragma unroll
     for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-    recon_poly<real, 2>(s, a0, a1, a2, k, P2);
+    recon_poly<real, 2>(s, a0, a1, a2, k, P2, om ? &wk : nullptr);
+    if (om) omin = omin < wk ? omin : wk;
     ql[c] = P2[0];
     qld[c] = P2[1] * inv_dn;
 #pragma unroll
     for (int m = 0; m < 5; ++m) s[m] = Q[5 - m][c];
-    recon_poly<real, 2>(s, a3, a2, a1, k, P2);
+    recon_poly<real, 2>(s, a3, a2, a1, k, P2, om ? &wk : nullptr);
+    if (om) omin = omin < wk ? omin : wk;
     qr[c] = P2[0];
     qrd[c] = -P2[1] * inv_dn;
   }
@@ -575,6 +570,7 @@ DFW_HD void normal_sweep(const real (*cell)[4], real a0, real a1, real a2, real 
   from_recon<CHAR>(B, qr, wr);
   from_recon<CHAR>(B, qld, wln);
   from_recon<CHAR>(B, qrd, wrn);
+  if (om) *om = omin;  // time-limiter weight of the interface (eq. (29)): both sides, all components
 }
 
 // ------------------------------------------------------------------------------------------------

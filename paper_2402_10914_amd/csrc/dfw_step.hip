@@ -232,6 +232,8 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   const int f = f0 + fl, t = t0 - 2 + rr;
   const bool live1 = f <= Nn && t < Nt + 2;
   real wln[4] = {0, 0, 0, 0}, wrn[4] = {0, 0, 0, 0};
+  real om = real(1);  // time-limiter weight of this interface segment, from the normal sweep
+  real* const omp = (OUT & OUT_OMEGA) ? &om : nullptr;
 
   // ---- normal sweep (Section 3.1): line values of both sides and their normal derivatives
   if (live1) {
@@ -243,10 +245,10 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
     real wl[4], wr[4];
     if (S.cw)  // uniform over the launch
       normal_sweep<real, false>(cell, sA[rr][fl], sA[rr][fl + 1], sA[rr][fl + 2], sA[rr][fl + 3], inv_dn, k, wl, wr,
-                                wln, wrn);
+                                wln, wrn, omp);
     else
       normal_sweep<real, true>(cell, sA[rr][fl], sA[rr][fl + 1], sA[rr][fl + 2], sA[rr][fl + 3], inv_dn, k, wl, wr,
-                               wln, wrn);
+                               wln, wrn, omp);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       sLine[c][tid] = wl[c];
@@ -277,15 +279,6 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   else
     segment_fluxes<real, FLUX, (OUT & OUT_F) != 0, (OUT & OUT_DF) != 0, true>(wa, wb, line, al, wln, wrn, dt, inv_dt,
                                                                               k, Fs, Fts, dfp);
-  real om = real(1);
-  if (OUT & OUT_OMEGA) {  // eq. (29), from the six cells of this segment's row
-    real cell[6][4];
-#pragma unroll
-    for (int m = 0; m < 6; ++m)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) cell[m][c] = sW[c][rr][fl + m];
-    om = S.cw ? time_limiter_omega<real, false>(cell, k) : time_limiter_omega<real, true>(cell, k);
-  }
   // ---- write face sums (quadrature weights 1/2), components back to the global order
   const size_t fstride = dir == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
   real* Fo = dir == 0 ? FX + (size_t)t * (nx + 1) + f : FY + (size_t)f * nx + t;
