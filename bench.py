@@ -80,17 +80,17 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(prob, steps):
+def cpu_baseline(prob, steps, time_limiter=0, time_scheme=0):
     """The oracle as it stands on this host: `steps` steps of the same grid."""
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     g = O.make_grid(prob.nx, prob.ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y)
-    p = O.make_params(flux=prob.flux, cfl=prob.cfl)
+    p = O.make_params(flux=prob.flux, cfl=prob.cfl, time_limiter=time_limiter, time_scheme=time_scheme)
     t0 = time.perf_counter()
     O.run(prob.W, prob.alpha, g, p, steps)
     el = time.perf_counter() - t0
     return {"value": prob.nx * prob.ny * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} S2O4 steps of the same {prob.nx}x{prob.ny} grid from the same initial state "
+            "sample": f"{steps} {'SSP-RK3' if time_scheme else 'S2O4'} steps of the same {prob.nx}x{prob.ny} grid from the same initial state "
                       f"({el:.1f} s, OpenMP over rows)"}
 
 
@@ -216,6 +216,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--mode", default="step", choices=["step", "copy", "adjoint"])
+    ap.add_argument("--time-limiter", action="store_true", help="the non-linear time limiter (the paper's GKS solver)")
+    ap.add_argument("--ssprk3", action="store_true", help="SSP-RK3 time steps (the paper's LF solver; LF workloads)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -235,7 +237,11 @@ def main():
     prob, dt_name = workload(args.workload)
     dtype = torch.float64 if dt_name == "f64" else torch.float32
     esize = 8 if dtype == torch.float64 else 4
-    params = api.Params(flux=prob.flux, cfl=prob.cfl)
+    tl, ts = int(args.time_limiter), int(args.ssprk3)
+    if ts and (prob.flux != api.FLUX_LF or tl):
+        raise SystemExit("--ssprk3 runs with the LF flux and without the time limiter")
+    params = api.Params(flux=prob.flux, cfl=prob.cfl, time_limiter=tl, time_scheme=ts)
+    default_form = not (tl or ts)
     st = api.Stepper.for_problem(prob, params, dtype)
     W0 = torch.tensor(prob.W, dtype=dtype, device="cuda")
     A0 = torch.tensor(prob.alpha, dtype=dtype, device="cuda")
@@ -271,6 +277,9 @@ def main():
         prof = kp.result()
         kernels = {k: {"avg_us": 1e3 * ms / n if n else None, "launches": n, "total_ms": ms}
                    for k, (ms, n) in prof.items()}
+    # the exact flop count covers the interface kernel of eq. (21) without the limiter; the other
+    # forms report times only
+    if not args.no_profile and default_form:
         ms1, n1 = prof["faces1"]
         avg_s = ms1 / n1 / 1e3
         faces = (prob.nx + 1) * prob.ny + prob.nx * (prob.ny + 1)
@@ -285,7 +294,7 @@ def main():
 
     hbm = BYTES_PER_CELL_UPDATE[esize] * value / 1e9
     out = {
-        "metric": "cell-updates/s per S2O4 step",
+        "metric": "cell-updates/s per S2O4 step" if not ts else "cell-updates/s per SSP-RK3 step",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -297,16 +306,17 @@ def main():
         "vs_baseline": None,
         "dtype": dt_name,
         "data": "synthetic",
-        "config": {"workload": f"{prob.nx}x{prob.ny} four-quadrant Riemann, GKS, WENO-AO+DF, S2O4, CFL 0.4, "
-                               "transmissive" if prob.name == "riemann4" else f"{prob.nx}x{prob.ny} {prob.name}",
+        "config": {"workload": (f"{prob.nx}x{prob.ny} four-quadrant Riemann, {'GKS' if prob.flux else 'LF'}, WENO-AO+DF, "
+                                f"{'SSP-RK3' if ts else 'S2O4'}{', time limiter' if tl else ''}, CFL 0.4, transmissive")
+                               if prob.name == "riemann4" else f"{prob.nx}x{prob.ny} {prob.name}",
                    "name": args.workload, "nx": prob.nx, "ny": prob.ny, "flux": "gks" if prob.flux else "lf",
-                   "parallelism": "single GPU"},
+                   "time_scheme": "ssprk3" if ts else "s2o4", "time_limiter": bool(tl), "parallelism": "single GPU"},
         "roofline": roofline,
         "hbm_algorithmic": {"bytes_per_cell_update": BYTES_PER_CELL_UPDATE[esize], "achieved_GBps": round(hbm, 1),
-                            "peak_GBps": PEAK_HBM, "frac": round(hbm / PEAK_HBM, 4)},
-        "flops_per_cell_update": flops.per_cell_update(prob.flux),
+                            "peak_GBps": PEAK_HBM, "frac": round(hbm / PEAK_HBM, 4)} if default_form else None,
+        "flops_per_cell_update": flops.per_cell_update(prob.flux) if default_form else None,
         "kernels": kernels,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps),
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps, tl, ts),
         "batched": None if args.no_batch else batch_compare(),
         "adjoint": None if args.no_adjoint else adjoint_compare(),
     }
