@@ -261,14 +261,14 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
     real b3 = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 + real(1421461.0 / 2275.0) * u4 * u4;
     real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
     real be[4] = {b0 + k.eps, b1 + k.eps, b2 + k.eps, b3 + k.eps};
-    const real i01 = real(1) / (be[0] * be[1]), i23 = real(1) / (be[2] * be[3]);
+    const real i01 = rcp_pos(be[0] * be[1]), i23 = rcp_pos(be[2] * be[3]);
     real ib[4] = {be[1] * i01, be[0] * i01, be[3] * i23, be[2] * i23}, r[4], w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       r[q] = tau * ib[q];
       w[q] = k.d[q] * (real(1) + r[q] * r[q]);
     }
-    real iws = real(1) / (w[0] + w[1] + w[2] + w[3]);
+    real iws = rcp_pos(w[0] + w[1] + w[2] + w[3]);
     real g3 = w[3] * iws;
     real g0 = w[0] * iws - g3 * k.dr[0];
     real g1 = w[1] * iws - g3 * k.dr[1];

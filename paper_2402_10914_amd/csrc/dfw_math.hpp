@@ -13,6 +13,38 @@
 
 namespace dfw {
 
+// Reciprocal of a positive, finite, normal number (the WENO-Z denominators: each is at least
+// eps^2).  On the device: the hardware reciprocal estimate refined by Newton-Raphson steps in fused
+// form, e = 1 - x r, r <- r + r e (two steps in FP64, one in FP32), within one unit in the last
+// place of 1/x, in 5 (FP64) or 3 (FP32) instructions instead of the ten-instruction IEEE division
+// sequence, whose scaling and fix-up steps only matter for zero, infinite or subnormal operands.
+// On the host (operation counts, host-side checks): the plain division.
+DFW_HD double rcp_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+DFW_HD float rcp_pos(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+#else
+  return 1.0f / x;
+#endif
+}
+
+template <class real>
+DFW_HD real rcp_pos(real x) {
+  return real(1) / x;
+}
+
 // Scheme constants in the working precision, converted once per kernel from the host values.
 template <class real>
 struct Coef {
@@ -221,7 +253,7 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
   // 1/(b_q + eps) from two divisions: 1/(B0 B1) and 1/(B2 B3)
   const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
-  const real i01 = real(1) / (B0 * B1), i23 = real(1) / (B2 * B3);
+  const real i01 = rcp_pos(B0 * B1), i23 = rcp_pos(B2 * B3);
   real r0 = tau * (B1 * i01), r1 = tau * (B0 * i01), r2 = tau * (B3 * i23), r3 = tau * (B2 * i23);
   if (om) {  // tau/(beta_min + eps) and tau/(beta_max + eps) are the largest and smallest ratio
     real rmax = r0 > r1 ? r0 : r1, rmin = r0 < r1 ? r0 : r1;
@@ -236,7 +268,7 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   real w1 = k.d[1] * (real(1) + r1 * r1);
   real w2 = k.d[2] * (real(1) + r2 * r2);
   real w3 = k.d[3] * (real(1) + r3 * r3);
-  real iws = real(1) / (w0 + w1 + w2 + w3);
+  real iws = rcp_pos(w0 + w1 + w2 + w3);
   real g3 = w3 * iws;
   real g0 = w0 * iws - g3 * k.dr[0];
   real g1 = w1 * iws - g3 * k.dr[1];
