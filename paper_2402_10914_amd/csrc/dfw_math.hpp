@@ -167,29 +167,48 @@ DFW_HD Basis<real> recon_basis(const real* wa, const real* wb, const Coef<real>&
 // ------------------------------------------------------------------------------------------------
 // Smoothness indicators beta_0..beta_3 of eq. (38) of the four WENO-AO stencils of a cell (five
 // averages Q[0..4] = Q_{i-2..i+2}): Jiang-Shu forms for the three quadratics, closed form for the
-// quartic.
+// quartic.  The differences they are built from are kept, since they also determine the candidate
+// polynomials: t_k is the second difference of stencil k (twice the xi^2 coefficient of p_k), s_0
+// twice the slope of p_0 at the cell centre, and u_1..u_4 the coefficients of the quartic in its
+// Legendre-type basis on the cell (u_4 is its xi^4 coefficient).
 // ------------------------------------------------------------------------------------------------
 template <class real>
-DFW_HD void weno_indicators(const real* Q, real* b) {
+struct WenoTerms {
+  real b[4];
+  real t0, t1, t2, s0, u1, u2, u3, u4;
+};
+
+template <class real>
+DFW_HD WenoTerms<real> weno_terms(const real* Q) {
   const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
   const real k1312 = real(13.0 / 12.0), k14 = real(0.25);
-  real t, s;
-  t = Q0 - real(2) * Q1 + Q2;
-  s = Q0 - real(4) * Q1 + real(3) * Q2;
-  b[0] = k1312 * t * t + k14 * s * s;
-  t = Q1 - real(2) * Q2 + Q3;
+  WenoTerms<real> T;
+  real s;
+  T.t0 = Q0 - real(2) * Q1 + Q2;
+  T.s0 = Q0 - real(4) * Q1 + real(3) * Q2;
+  T.b[0] = k1312 * T.t0 * T.t0 + k14 * T.s0 * T.s0;
+  T.t1 = Q1 - real(2) * Q2 + Q3;
   s = Q1 - Q3;
-  b[1] = k1312 * t * t + k14 * s * s;
-  t = Q2 - real(2) * Q3 + Q4;
+  T.b[1] = k1312 * T.t1 * T.t1 + k14 * s * s;
+  T.t2 = Q2 - real(2) * Q3 + Q4;
   s = real(3) * Q2 - real(4) * Q3 + Q4;
-  b[2] = k1312 * t * t + k14 * s * s;
-  real u1 = (real(11) * (Q0 - Q4) + real(82) * (Q3 - Q1)) * real(1.0 / 120.0);
-  real u2 = (real(40) * (Q1 + Q3) - real(3) * (Q0 + Q4) - real(74) * Q2) * real(1.0 / 56.0);
-  real u3 = (real(2) * (Q1 - Q3) + Q4 - Q0) * real(1.0 / 12.0);
-  real u4 = (Q0 - real(4) * Q1 + real(6) * Q2 - real(4) * Q3 + Q4) * real(1.0 / 24.0);
-  real e1 = u1 + real(0.1) * u3;
-  real e2 = u2 + real(123.0 / 455.0) * u4;
-  b[3] = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * u3 * u3 + real(1421461.0 / 2275.0) * u4 * u4;
+  T.b[2] = k1312 * T.t2 * T.t2 + k14 * s * s;
+  T.u1 = (real(11) * (Q0 - Q4) + real(82) * (Q3 - Q1)) * real(1.0 / 120.0);
+  T.u2 = (real(40) * (Q1 + Q3) - real(3) * (Q0 + Q4) - real(74) * Q2) * real(1.0 / 56.0);
+  T.u3 = (real(2) * (Q1 - Q3) + Q4 - Q0) * real(1.0 / 12.0);
+  T.u4 = (Q0 - real(4) * Q1 + real(6) * Q2 - real(4) * Q3 + Q4) * real(1.0 / 24.0);
+  const real e1 = T.u1 + real(0.1) * T.u3;
+  const real e2 = T.u2 + real(123.0 / 455.0) * T.u4;
+  T.b[3] = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * T.u3 * T.u3 +
+           real(1421461.0 / 2275.0) * T.u4 * T.u4;
+  return T;
+}
+
+template <class real>
+DFW_HD void weno_indicators(const real* Q, real* b) {
+  const WenoTerms<real> T = weno_terms(Q);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) b[q] = T.b[q];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -221,7 +240,7 @@ DFW_HD real time_limiter_weight(const real* Q, const Coef<real>& k) {
 template <class real, int NDEG, int RULE = -1>
 DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, real* P,
                        real* om = nullptr) {
-  const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
+  const real Q1 = Q[1], Q2 = Q[2], Q3 = Q[3];
   // candidate p1 (centred quadratic): coefficients of 1, xi, xi^2
   real p1_0 = (real(5) * Q2 + real(2) * Q3 - Q1) * real(1.0 / 6.0);
   real p1_1 = Q3 - Q2;
@@ -235,23 +254,11 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
     if (om) *om = time_limiter_weight(Q, k);
     return;
   }
-  real p0_0 = (real(2) * Q0 - real(7) * Q1 + real(11) * Q2) * real(1.0 / 6.0);
-  real p0_1 = Q0 - real(3) * Q1 + real(2) * Q2;
-  real p0_2 = real(0.5) * (Q0 + Q2) - Q1;
-  real p2_0 = (real(2) * Q2 + real(5) * Q3 - Q4) * real(1.0 / 6.0);
-  real p2_1 = Q3 - Q2;
-  real p2_2 = real(0.5) * (Q2 + Q4) - Q3;
-  real c0 = (real(2) * Q0 - real(13) * Q1 + real(47) * Q2 + real(27) * Q3 - real(3) * Q4) * real(1.0 / 60.0);
-  real c1 = (Q1 - real(15) * Q2 + real(15) * Q3 - Q4) * real(1.0 / 12.0);
-  real c2 = (-Q0 + real(6) * Q1 - real(8) * Q2 + real(2) * Q3 + Q4) * real(0.125);
-  real c3 = (-Q1 + real(3) * Q2 - real(3) * Q3 + Q4) * real(1.0 / 6.0);
-  real c4 = (Q0 - real(4) * Q1 + real(6) * Q2 - real(4) * Q3 + Q4) * real(1.0 / 24.0);
-  real bq[4];
-  weno_indicators(Q, bq);
-  const real b0 = bq[0], b1 = bq[1], b2 = bq[2], b3 = bq[3];
+  const WenoTerms<real> T = weno_terms(Q);
+  const real b0 = T.b[0], b1 = T.b[1], b2 = T.b[2], b3 = T.b[3];
   // WENO-Z weights, eqs. (36)-(37)
   real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
-  // 1/(b_q + eps) from two divisions: 1/(B0 B1) and 1/(B2 B3)
+  // 1/(b_q + eps) from two reciprocals: 1/(B0 B1) and 1/(B2 B3)
   const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
   const real i01 = rcp_pos(B0 * B1), i23 = rcp_pos(B2 * B3);
   real r0 = tau * (B1 * i01), r1 = tau * (B0 * i01), r2 = tau * (B3 * i23), r3 = tau * (B2 * i23);
@@ -274,11 +281,25 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   real g1 = w1 * iws - g3 * k.dr[1];
   real g2 = w2 * iws - g3 * k.dr[2];
   real h3 = g3 * k.inv_d3;
-  P[0] = g0 * p0_0 + g1 * p1_0 + g2 * p2_0 + h3 * c0;
-  if (NDEG > 1) P[1] = g0 * p0_1 + g1 * p1_1 + g2 * p2_1 + h3 * c1;
-  if (NDEG > 2) P[2] = g0 * p0_2 + g1 * p1_2 + g2 * p2_2 + h3 * c2;
-  if (NDEG > 3) P[3] = h3 * c3;
-  if (NDEG > 4) P[4] = h3 * c4;
+  // Coefficients of xi^1..xi^4 of the candidates, written through the indicator terms (exact
+  // identities of the cell-average fits): p_k has xi^2 coefficient t_k/2; p_0 has slope
+  // (s_0 + t_0)/2 at the edge, p_1 and p_2 both Q3 - Q2; the quartic p_3 has c_4 = u_4,
+  // c_3 = u_3 + 2 u_4, c_2 = u_2 + 3/2 u_3 + 9/7 u_4, c_1 = u_1 + u_2 + 3/5 u_3 + 2/7 u_4.
+  const real p0_1 = real(0.5) * (T.s0 + T.t0);
+  const real c1 = T.u1 + T.u2 + real(0.6) * T.u3 + real(2.0 / 7.0) * T.u4;
+  const real c2 = T.u2 + real(1.5) * T.u3 + real(9.0 / 7.0) * T.u4;
+  const real c3 = T.u3 + real(2) * T.u4;
+  const real P1 = g0 * p0_1 + (g1 + g2) * p1_1 + h3 * c1;
+  const real P2 = real(0.5) * (g0 * T.t0 + g1 * T.t1 + g2 * T.t2) + h3 * c2;
+  const real P3 = h3 * c3, P4 = h3 * T.u4;
+  // Every candidate has the cell average Q_i and g0 + g1 + g2 + h3 = 1, so the combination does
+  // too; its value at the edge follows from that condition: the mean of xi^n over [-1, 0] is
+  // (-1)^n / (n + 1).
+  P[0] = Q2 + real(0.5) * P1 - real(1.0 / 3.0) * P2 + real(0.25) * P3 - real(0.2) * P4;
+  if (NDEG > 1) P[1] = P1;
+  if (NDEG > 2) P[2] = P2;
+  if (NDEG > 3) P[3] = P3;
+  if (NDEG > 4) P[4] = P4;
 }
 
 // Gauss points of a segment [-1, 0] (in units of its length): -1/2 -+ sqrt(3)/6.
