@@ -9,6 +9,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #define DFW_HD __host__ __device__ __forceinline__
 
 namespace dfw {
@@ -183,20 +185,21 @@ DFW_HD WenoTerms<real> weno_terms(const real* Q) {
   const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
   const real k1312 = real(13.0 / 12.0), k14 = real(0.25);
   WenoTerms<real> T;
-  real s;
   T.t0 = Q0 - real(2) * Q1 + Q2;
-  T.s0 = Q0 - real(4) * Q1 + real(3) * Q2;
-  T.b[0] = k1312 * T.t0 * T.t0 + k14 * T.s0 * T.s0;
   T.t1 = Q1 - real(2) * Q2 + Q3;
-  s = Q1 - Q3;
-  T.b[1] = k1312 * T.t1 * T.t1 + k14 * s * s;
   T.t2 = Q2 - real(2) * Q3 + Q4;
-  s = real(3) * Q2 - real(4) * Q3 + Q4;
-  T.b[2] = k1312 * T.t2 * T.t2 + k14 * s * s;
-  T.u1 = (real(11) * (Q0 - Q4) + real(82) * (Q3 - Q1)) * real(1.0 / 120.0);
-  T.u2 = (real(40) * (Q1 + Q3) - real(3) * (Q0 + Q4) - real(74) * Q2) * real(1.0 / 56.0);
-  T.u3 = (real(2) * (Q1 - Q3) + Q4 - Q0) * real(1.0 / 12.0);
-  T.u4 = (Q0 - real(4) * Q1 + real(6) * Q2 - real(4) * Q3 + Q4) * real(1.0 / 24.0);
+  T.s0 = Q0 - real(4) * Q1 + real(3) * Q2;
+  const real s1 = Q1 - Q3;
+  const real s2 = T.t2 - real(2) * (Q3 - Q2);  // 3 Q2 - 4 Q3 + Q4
+  T.b[0] = k1312 * T.t0 * T.t0 + k14 * T.s0 * T.s0;
+  T.b[1] = k1312 * T.t1 * T.t1 + k14 * s1 * s1;
+  T.b[2] = k1312 * T.t2 * T.t2 + k14 * s2 * s2;
+  // the quartic's coefficients from the same differences (exact identities of its cell-average fit)
+  const real d40 = Q4 - Q0;
+  T.u1 = (real(-11) * d40 - real(82) * s1) * real(1.0 / 120.0);
+  T.u2 = (real(34) * T.t1 - real(3) * (T.t0 + T.t2)) * real(1.0 / 56.0);
+  T.u3 = (real(2) * s1 + d40) * real(1.0 / 12.0);
+  T.u4 = (T.t0 - real(2) * T.t1 + T.t2) * real(1.0 / 24.0);
   const real e1 = T.u1 + real(0.1) * T.u3;
   const real e2 = T.u2 + real(123.0 / 455.0) * T.u4;
   T.b[3] = e1 * e1 + real(13.0 / 3.0) * e2 * e2 + real(781.0 / 20.0) * T.u3 * T.u3 +
@@ -258,10 +261,19 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   const real b0 = T.b[0], b1 = T.b[1], b2 = T.b[2], b3 = T.b[3];
   // WENO-Z weights, eqs. (36)-(37)
   real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
-  // 1/(b_q + eps) from two reciprocals: 1/(B0 B1) and 1/(B2 B3)
+  // r_q = tau / (b_q + eps) from products of the B_q and few reciprocals: one of B0 B1 B2 B3 in
+  // FP64 (a product of four numbers in [eps, 1e75] stays normal), 1/(B0 B1) and 1/(B2 B3) in FP32
   const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
-  const real i01 = rcp_pos(B0 * B1), i23 = rcp_pos(B2 * B3);
-  real r0 = tau * (B1 * i01), r1 = tau * (B0 * i01), r2 = tau * (B3 * i23), r3 = tau * (B2 * i23);
+  const real P01 = B0 * B1, P23 = B2 * B3;
+  real r0, r1, r2, r3;
+  if constexpr (std::is_same<real, float>::value) {
+    const real i01 = rcp_pos(P01), i23 = rcp_pos(P23);
+    r0 = tau * (B1 * i01), r1 = tau * (B0 * i01), r2 = tau * (B3 * i23), r3 = tau * (B2 * i23);
+  } else {
+    const real ti = tau * rcp_pos(P01 * P23);
+    const real t23 = ti * P23, t01 = ti * P01;
+    r0 = t23 * B1, r1 = t23 * B0, r2 = t01 * B3, r3 = t01 * B2;
+  }
   if (om) {  // tau/(beta_min + eps) and tau/(beta_max + eps) are the largest and smallest ratio
     real rmax = r0 > r1 ? r0 : r1, rmin = r0 < r1 ? r0 : r1;
     rmax = rmax > r2 ? rmax : r2;
