@@ -170,14 +170,15 @@ DFW_HD Basis<real> recon_basis(const real* wa, const real* wb, const Coef<real>&
 // Smoothness indicators beta_0..beta_3 of eq. (38) of the four WENO-AO stencils of a cell (five
 // averages Q[0..4] = Q_{i-2..i+2}): Jiang-Shu forms for the three quadratics, closed form for the
 // quartic.  The differences they are built from are kept, since they also determine the candidate
-// polynomials: t_k is the second difference of stencil k (twice the xi^2 coefficient of p_k), s_0
-// twice the slope of p_0 at the cell centre, and u_1..u_4 the coefficients of the quartic in its
-// Legendre-type basis on the cell (u_4 is its xi^4 coefficient).
+// polynomials: t_k is the second difference of stencil k (twice the xi^2 coefficient of p_k), s_k
+// twice the slope of p_k at the cell centre (with the sign of its Jiang-Shu form: +p_0', -p_1',
+// -p_2'), and u_1..u_4 the coefficients of the quartic in its Legendre-type basis on the cell: in
+// zeta = xi + 1/2 its zeta^1..zeta^4 coefficients are u_1 - 3/20 u_3, u_2 - 3/14 u_4, u_3 and u_4.
 // ------------------------------------------------------------------------------------------------
 template <class real>
 struct WenoTerms {
   real b[4];
-  real t0, t1, t2, s0, u1, u2, u3, u4;
+  real t0, t1, t2, s0, s1, s2, u1, u2, u3, u4;
 };
 
 template <class real>
@@ -189,16 +190,16 @@ DFW_HD WenoTerms<real> weno_terms(const real* Q) {
   T.t1 = Q1 - real(2) * Q2 + Q3;
   T.t2 = Q2 - real(2) * Q3 + Q4;
   T.s0 = Q0 - real(4) * Q1 + real(3) * Q2;
-  const real s1 = Q1 - Q3;
-  const real s2 = T.t2 - real(2) * (Q3 - Q2);  // 3 Q2 - 4 Q3 + Q4
+  T.s1 = Q1 - Q3;
+  T.s2 = T.t2 - real(2) * (Q3 - Q2);  // 3 Q2 - 4 Q3 + Q4
   T.b[0] = k1312 * T.t0 * T.t0 + k14 * T.s0 * T.s0;
-  T.b[1] = k1312 * T.t1 * T.t1 + k14 * s1 * s1;
-  T.b[2] = k1312 * T.t2 * T.t2 + k14 * s2 * s2;
+  T.b[1] = k1312 * T.t1 * T.t1 + k14 * T.s1 * T.s1;
+  T.b[2] = k1312 * T.t2 * T.t2 + k14 * T.s2 * T.s2;
   // the quartic's coefficients from the same differences (exact identities of its cell-average fit)
   const real d40 = Q4 - Q0;
-  T.u1 = (real(-11) * d40 - real(82) * s1) * real(1.0 / 120.0);
+  T.u1 = (real(-11) * d40 - real(82) * T.s1) * real(1.0 / 120.0);
   T.u2 = (real(34) * T.t1 - real(3) * (T.t0 + T.t2)) * real(1.0 / 56.0);
-  T.u3 = (real(2) * s1 + d40) * real(1.0 / 12.0);
+  T.u3 = (real(2) * T.s1 + d40) * real(1.0 / 12.0);
   T.u4 = (T.t0 - real(2) * T.t1 + T.t2) * real(1.0 / 24.0);
   const real e1 = T.u1 + real(0.1) * T.u3;
   const real e2 = T.u2 + real(123.0 / 455.0) * T.u4;
@@ -322,6 +323,61 @@ template <class real>
 DFW_HD void eval_poly_at(const real* P, real xi, real& val, real& der) {
   val = (((P[4] * xi + P[3]) * xi + P[2]) * xi + P[1]) * xi + P[0];
   der = ((real(4) * P[4] * xi + real(3) * P[3]) * xi + real(2) * P[2]) * xi + P[1];
+}
+
+// The hybrid reconstruction of one cell evaluated at the two Gauss points of the segment, xi =
+// kXiGp0, kXiGp1 (the tangential sweep): values v[g] and slopes d[g] (per unit xi).  The same
+// polynomial as recon_poly, taken in the centred variable zeta = xi + 1/2, where the Gauss points
+// are zeta = -/+ delta with delta^2 = 1/12:  P = D0 + D1 zeta + ... + D4 zeta^4 with
+//   D1 = (g0 s0 - g1 s1 - g2 s2)/2 + h3 (u1 - 3/20 u3),  D2 = (g0 t0 + g1 t1 + g2 t2)/2 + h3 (u2 - 3/14 u4),
+//   D3 = h3 u3,  D4 = h3 u4,
+// and D0 fixed by the cell mean (D0 = Q_i - D2/12 - D4/80), so that
+//   v = Q_i - D4/180 -/+ delta (D1 + D3/12),   d = D1 + D3/4 -/+ delta (2 D2 + D4/3).
+// DF branch: D1 = alpha_i (Q3 - Q1)/2, D2 = alpha_i t1/2, D3 = D4 = 0.
+template <class real, int RULE = -1>
+DFW_HD void recon_gauss(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, real* v, real* d) {
+  const real Q2 = Q[2];
+  real D1, D2, D3 = real(0), D4 = real(0);
+  if (df_switch<RULE>(a_lo, a_c, a_hi, k)) {
+    D1 = a_c * (real(0.5) * (Q[3] - Q[1]));
+    D2 = a_c * (real(0.5) * (Q[1] - real(2) * Q2 + Q[3]));
+  } else {
+    const WenoTerms<real> T = weno_terms(Q);
+    const real b0 = T.b[0], b1 = T.b[1], b2 = T.b[2], b3 = T.b[3];
+    const real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
+    const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
+    const real P01 = B0 * B1, P23 = B2 * B3;
+    real r0, r1, r2, r3;
+    if constexpr (std::is_same<real, float>::value) {
+      const real i01 = rcp_pos(P01), i23 = rcp_pos(P23);
+      r0 = tau * (B1 * i01), r1 = tau * (B0 * i01), r2 = tau * (B3 * i23), r3 = tau * (B2 * i23);
+    } else {
+      const real ti = tau * rcp_pos(P01 * P23);
+      const real t23 = ti * P23, t01 = ti * P01;
+      r0 = t23 * B1, r1 = t23 * B0, r2 = t01 * B3, r3 = t01 * B2;
+    }
+    const real w0 = k.d[0] * (real(1) + r0 * r0);
+    const real w1 = k.d[1] * (real(1) + r1 * r1);
+    const real w2 = k.d[2] * (real(1) + r2 * r2);
+    const real w3 = k.d[3] * (real(1) + r3 * r3);
+    const real iws = rcp_pos(w0 + w1 + w2 + w3);
+    const real g3 = w3 * iws;
+    const real g0 = w0 * iws - g3 * k.dr[0];
+    const real g1 = w1 * iws - g3 * k.dr[1];
+    const real g2 = w2 * iws - g3 * k.dr[2];
+    const real h3 = g3 * k.inv_d3;
+    D1 = real(0.5) * (g0 * T.s0 - g1 * T.s1 - g2 * T.s2) + h3 * (T.u1 - real(0.15) * T.u3);
+    D2 = real(0.5) * (g0 * T.t0 + g1 * T.t1 + g2 * T.t2) + h3 * (T.u2 - real(3.0 / 14.0) * T.u4);
+    D3 = h3 * T.u3;
+    D4 = h3 * T.u4;
+  }
+  const real dl = real(0.28867513459481288225);  // sqrt(3)/6
+  const real ev = Q2 - real(1.0 / 180.0) * D4, od = dl * (D1 + real(1.0 / 12.0) * D3);
+  const real evd = D1 + real(0.25) * D3, odd = dl * (real(2) * D2 + real(1.0 / 3.0) * D4);
+  v[0] = ev - od;
+  v[1] = ev + od;
+  d[0] = evd - odd;
+  d[1] = evd + odd;
 }
 
 
@@ -664,17 +720,14 @@ DFW_HD void segment_fluxes(const real* wa, const real* wb, LineFn line, const re
     real qv[2][4], qd[2][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      real s[5], Pc[5];
+      real s[5], v[2], d[2];
 #pragma unroll
       for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-      recon_poly<real, 5>(s, alpha[side][0], alpha[side][1], alpha[side][2], k, Pc);
-      real v0, d0, v1, d1;
-      eval_poly_at(Pc, real(kXiGp0), v0, d0);
-      eval_poly_at(Pc, real(kXiGp1), v1, d1);
-      qv[0][c] = v0;
-      qv[1][c] = v1;
-      qd[0][c] = d0 * inv_dt;
-      qd[1][c] = d1 * inv_dt;
+      recon_gauss<real>(s, alpha[side][0], alpha[side][1], alpha[side][2], k, v, d);
+      qv[0][c] = v[0];
+      qv[1][c] = v[1];
+      qd[0][c] = d[0] * inv_dt;
+      qd[1][c] = d[1] * inv_dt;
     }
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
