@@ -480,13 +480,14 @@ DFW_HD void full_recursion(real* m, int from, int to, real U, real h) {
   for (int n = from; n + 2 <= to; ++n) m[n + 2] = U * m[n + 1] + real(n + 1) * h * m[n];
 }
 
-// side: 0 full space, +1 u > 0, -1 u < 0
+// side: 0 full space, +1 u > 0, -1 u < 0.  h = 1/(2 lam), which the callers form as p/rho from the
+// reciprocal of the density they already hold (the same value as 0.5/lam, also for p = 0 and on
+// failing states, without a division).
 template <class real>
-DFW_HD void maxwell_moments(real U, real V, real lam, int side, const Coef<real>& k, Mom<real>& M) {
+DFW_HD void maxwell_moments(real U, real V, real lam, real h, int side, const Coef<real>& k, Mom<real>& M) {
   M.U = U;
   M.V = V;
   M.lam = lam;
-  real h = real(0.5) / lam;
   M.h = h;
   if (side == 0) {
     M.mu[0] = real(1);
@@ -513,24 +514,51 @@ DFW_HD void maxwell_moments(real U, real V, real lam, int side, const Coef<real>
 }
 
 template <class real>
+DFW_HD void maxwell_moments(real U, real V, real lam, int side, const Coef<real>& k, Mom<real>& M) {
+  maxwell_moments(U, V, lam, real(0.5) / lam, side, k, M);
+}
+
+template <class real>
 DFW_HD real mom(const Mom<real>& M, int a, int b, int c) {
   return M.mu[a] * M.mv[b] * M.mx[c];
 }
 
-// <(s . psi) u^a v^b xi^2c>, s . psi = s0 + s1 u + s2 v + s3 (u^2 + v^2 + xi^2)/2
+// <(s . psi) u^a v^b xi^2c>, s . psi = s0 + s1 u + s2 v + s3 (u^2 + v^2 + xi^2)/2.  With the v- and
+// xi-moments folded first it is a three-term form in the u-moments,
+//   <(s . psi) u^a v^b xi^2c> = A mu[a] + B mu[a+1] + C mu[a+2],
+//   A = s0 mv[b] mx[c] + s2 mv[b+1] mx[c] + s3/2 (mv[b+2] mx[c] + mv[b] mx[c+1]),
+//   B = s1 mv[b] mx[c],  C = s3/2 mv[b] mx[c],
+// whose coefficients depend on (s, b, c) only: calls with the same slope and v-power share them.
 template <class real>
-DFW_HD real mom_s(const Mom<real>& M, const real* s, int a, int b, int c) {
-  return s[0] * mom(M, a, b, c) + s[1] * mom(M, a + 1, b, c) + s[2] * mom(M, a, b + 1, c) +
-         real(0.5) * s[3] * (mom(M, a + 2, b, c) + mom(M, a, b + 2, c) + mom(M, a, b, c + 1));
+struct SForm {
+  real A, B, C;
+};
+
+template <class real>
+DFW_HD SForm<real> s_form(const Mom<real>& M, const real* s, int b, int c) {
+  const real vx = M.mv[b] * M.mx[c];
+  const real hs3 = real(0.5) * s[3];
+  SForm<real> f;
+  f.A = s[0] * vx + s[2] * (M.mv[b + 1] * M.mx[c]) + hs3 * (M.mv[b + 2] * M.mx[c] + M.mv[b] * M.mx[c + 1]);
+  f.B = s[1] * vx;
+  f.C = hs3 * vx;
+  return f;
+}
+
+template <class real>
+DFW_HD real s_apply(const SForm<real>& f, const real* mu, int a) {
+  return f.A * mu[a] + f.B * mu[a + 1] + f.C * mu[a + 2];
 }
 
 // <(s . psi) u^a v^b psi>  (4 components)
 template <class real>
 DFW_HD void mom_s_psi(const Mom<real>& M, const real* s, int a, int b, real* out) {
-  out[0] = mom_s(M, s, a, b, 0);
-  out[1] = mom_s(M, s, a + 1, b, 0);
-  out[2] = mom_s(M, s, a, b + 1, 0);
-  out[3] = real(0.5) * (mom_s(M, s, a + 2, b, 0) + mom_s(M, s, a, b + 2, 0) + mom_s(M, s, a, b, 1));
+  const SForm<real> f0 = s_form(M, s, b, 0), f1 = s_form(M, s, b + 1, 0), f2 = s_form(M, s, b + 2, 0);
+  const SForm<real> fx = s_form(M, s, b, 1);
+  out[0] = s_apply(f0, M.mu, a);
+  out[1] = s_apply(f0, M.mu, a + 1);
+  out[2] = s_apply(f1, M.mu, a);
+  out[3] = real(0.5) * (s_apply(f0, M.mu, a + 2) + s_apply(f2, M.mu, a) + s_apply(fx, M.mu, a));
 }
 
 // <u^a v^b psi>
@@ -578,7 +606,7 @@ DFW_HD void gks_flux(const real* wl, const real* wln, const real* wlt, const rea
     const Prim<real>& q = side == 0 ? ql : qr;
     real lam = real(0.5) * q.r / q.p;
     Mom<real> M;
-    maxwell_moments(q.u, q.v, lam, side == 0 ? 1 : -1, k, M);
+    maxwell_moments(q.u, q.v, lam, q.p * q.ir, side == 0 ? 1 : -1, k, M);
     real g[4], a[4], b[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) g[c] = wn[c] * q.ir;
@@ -611,7 +639,7 @@ DFW_HD void gks_flux(const real* wl, const real* wln, const real* wlt, const rea
   real pc = k.gm1 * (Wc[3] - real(0.5) * (Wc[1] * Uc + Wc[2] * Vc));
   real lamc = real(0.5) * Wc[0] / pc;
   Mom<real> M;
-  maxwell_moments(Uc, Vc, lamc, 0, k, M);
+  maxwell_moments(Uc, Vc, lamc, pc * irc, 0, k, M);
   real g[4], ac[4], bc[4], Ac[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) g[c] = Wcn[c] * irc;

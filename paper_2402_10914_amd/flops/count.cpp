@@ -2,8 +2,12 @@
 // arithmetic (dfw_math.hpp) on the host with a scalar that counts every add, multiply, divide,
 // square root, exponential and erfc.  Counting convention: each of these is one flop (a fused
 // multiply-add counts as its multiply and its add); comparisons, absolute values and negations
-// are not counted.  The data is smooth (WENO-AO branch everywhere), the common path; the DF branch
-// is cheaper.  Prints JSON.
+// are not counted.  Operations the compiler evaluates itself are not counted either: the scalar
+// knows which values are constants of the source (literals and arithmetic on literals only), so an
+// operation on two constants, and a multiplication or division by the constant 1 (or -1, a
+// negation), count nothing, as on the GPU, where they never execute.  Inputs (states, scheme
+// coefficients, time step) are run-time values.  The data is smooth (WENO-AO branch everywhere),
+// the common path; the DF branch is cheaper.  Prints JSON.
 #include <cmath>
 #include <cstdio>
 
@@ -13,24 +17,53 @@ namespace cnt {
 long long n_add = 0, n_mul = 0, n_div = 0, n_sqrt = 0, n_exp = 0, n_erfc = 0;
 struct C {
   double v;
-  C() : v(0) {}
-  C(double x) : v(x) {}
-  C(int x) : v(x) {}
+  bool lit;  // a constant of the source
+  C() : v(0), lit(true) {}
+  C(double x) : v(x), lit(true) {}
+  C(int x) : v(x), lit(true) {}
 };
-inline C operator+(C a, C b) { ++n_add; return C(a.v + b.v); }
-inline C operator-(C a, C b) { ++n_add; return C(a.v - b.v); }
-inline C operator*(C a, C b) { ++n_mul; return C(a.v * b.v); }
-inline C operator/(C a, C b) { ++n_div; return C(a.v / b.v); }
-inline C operator-(C a) { return C(-a.v); }
+inline C value(double x, bool lit) {
+  C c(x);
+  c.lit = lit;
+  return c;
+}
+inline C run(double x) { return value(x, false); }  // a run-time input
+inline bool is(C a, double x) { return a.lit && a.v == x; }
+inline C operator-(C a) { return value(-a.v, a.lit); }
+inline C operator+(C a, C b) {
+  if (a.lit && b.lit) return value(a.v + b.v, true);
+  ++n_add;
+  return run(a.v + b.v);
+}
+inline C operator-(C a, C b) {
+  if (a.lit && b.lit) return value(a.v - b.v, true);
+  ++n_add;
+  return run(a.v - b.v);
+}
+inline C operator*(C a, C b) {
+  if (a.lit && b.lit) return value(a.v * b.v, true);
+  if (is(a, 1.0)) return b;
+  if (is(b, 1.0)) return a;
+  if (is(a, -1.0)) return -b;
+  if (is(b, -1.0)) return -a;
+  ++n_mul;
+  return run(a.v * b.v);
+}
+inline C operator/(C a, C b) {
+  if (a.lit && b.lit) return value(a.v / b.v, true);
+  if (is(b, 1.0)) return a;
+  ++n_div;
+  return run(a.v / b.v);
+}
 inline C& operator+=(C& a, C b) { a = a + b; return a; }
 inline C& operator*=(C& a, C b) { a = a * b; return a; }
 inline bool operator<(C a, C b) { return a.v < b.v; }
 inline bool operator>(C a, C b) { return a.v > b.v; }
 inline bool operator>=(C a, C b) { return a.v >= b.v; }
-inline C sqrt(C a) { ++n_sqrt; return C(std::sqrt(a.v)); }
-inline C exp(C a) { ++n_exp; return C(std::exp(a.v)); }
-inline C erfc(C a) { ++n_erfc; return C(std::erfc(a.v)); }
-inline C fabs(C a) { return C(std::fabs(a.v)); }
+inline C sqrt(C a) { if (a.lit) return value(std::sqrt(a.v), true); ++n_sqrt; return run(std::sqrt(a.v)); }
+inline C exp(C a) { if (a.lit) return value(std::exp(a.v), true); ++n_exp; return run(std::exp(a.v)); }
+inline C erfc(C a) { if (a.lit) return value(std::erfc(a.v), true); ++n_erfc; return run(std::erfc(a.v)); }
+inline C fabs(C a) { return value(std::fabs(a.v), a.lit); }
 long long total() { return n_add + n_mul + n_div + n_sqrt + n_exp + n_erfc; }
 void reset() { n_add = n_mul = n_div = n_sqrt = n_exp = n_erfc = 0; }
 }  // namespace cnt
@@ -38,22 +71,24 @@ void reset() { n_add = n_mul = n_div = n_sqrt = n_exp = n_erfc = 0; }
 using cnt::C;
 
 static dfw::Coef<C> coef() {
+  using cnt::run;
   dfw::Coef<C> k;
   double g = 1.4, dh = 0.85, dl = 0.85;
-  k.gamma = g; k.gm1 = g - 1; k.inv_gm1 = 1 / (g - 1); k.alpha_thres = 0.5; k.eps = 1e-6;
-  k.c1 = 0.01; k.c2 = 5.0; k.K = (4 - 2 * g) / (g - 1);
+  k.gamma = run(g); k.gm1 = run(g - 1); k.inv_gm1 = run(1 / (g - 1)); k.alpha_thres = run(0.5); k.eps = run(1e-6);
+  k.c1 = run(0.01); k.c2 = run(5.0); k.K = run((4 - 2 * g) / (g - 1));
   double d[4] = {(1 - dh) * (1 - dl) / 2, (1 - dh) * dl, (1 - dh) * (1 - dl) / 2, dh};
-  for (int i = 0; i < 4; ++i) k.d[i] = d[i];
-  for (int i = 0; i < 3; ++i) k.dr[i] = d[i] / d[3];
-  k.inv_d3 = 1 / d[3];
-  k.K2 = k.K.v + 2; k.k4K2 = 4 / (k.K.v + 2);
+  for (int i = 0; i < 4; ++i) k.d[i] = run(d[i]);
+  for (int i = 0; i < 3; ++i) k.dr[i] = run(d[i] / d[3]);
+  k.inv_d3 = run(1 / d[3]);
+  k.K2 = run(k.K.v + 2); k.k4K2 = run(4 / (k.K.v + 2));
   k.sw_rule = 0;
   return k;
 }
 
 static void state(double x, C* w) {  // smooth sample state
   double r = 1 + 0.2 * std::sin(x), u = 0.3 + 0.1 * std::cos(x), v = -0.2 + 0.1 * std::sin(2 * x), p = 1 + 0.1 * std::cos(x);
-  w[0] = r; w[1] = r * u; w[2] = r * v; w[3] = p / 0.4 + 0.5 * r * (u * u + v * v);
+  w[0] = cnt::run(r); w[1] = cnt::run(r * u); w[2] = cnt::run(r * v);
+  w[3] = cnt::run(p / 0.4 + 0.5 * r * (u * u + v * v));
 }
 
 struct Count { long long total, div, sqrt_, exp_, erfc_; };
@@ -67,11 +102,11 @@ static Count segment() {
   for (int s = 0; s < 2; ++s) for (int m = 0; m < 5; ++m) state(0.05 * (m + 3 * s), lines[s][m]);
   for (int c = 0; c < 4; ++c) { wln[c] = wln[c] * C(0.01); wrn[c] = wrn[c] * C(0.01); }
   C al[2][3];
-  for (int s = 0; s < 2; ++s) for (int q = 0; q < 3; ++q) al[s][q] = 1.0;
+  for (int s = 0; s < 2; ++s) for (int q = 0; q < 3; ++q) al[s][q] = cnt::run(1.0);
   auto line = [&](int side, int m, int c) -> C { return lines[side][m][c]; };
   C Fs[4], Fts[4], dfp;
   cnt::reset();
-  dfw::segment_fluxes<C, FLUX, F, DF>(wa, wb, line, al, wln, wrn, C(1e-3), C(100.0), k, Fs, Fts, dfp);
+  dfw::segment_fluxes<C, FLUX, F, DF>(wa, wb, line, al, wln, wrn, cnt::run(1e-3), cnt::run(100.0), k, Fs, Fts, dfp);
   return snap();
 }
 
@@ -80,7 +115,8 @@ static Count normal() {
   C cell[6][4], wl[4], wr[4], wln[4], wrn[4];
   for (int m = 0; m < 6; ++m) state(0.05 * m, cell[m]);
   cnt::reset();
-  dfw::normal_sweep<C>(cell, C(1.0), C(1.0), C(1.0), C(1.0), C(100.0), k, wl, wr, wln, wrn);
+  const C one = cnt::run(1.0);
+  dfw::normal_sweep<C>(cell, one, one, one, one, cnt::run(100.0), k, wl, wr, wln, wrn);
   return snap();
 }
 
