@@ -355,6 +355,119 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
   lQ[3] += real(2) * l10 * i6 + l11 + real(0.5) * l12;
 }
 
+// Reverse of recon_gauss: the adjoints lv, ld of the values and slopes at the two Gauss points ->
+// lQ (5, accumulated) and the DF of the centre cell (DF branch).  Also returns the forward values
+// and slopes (v, d), as recon_gauss computes them up to rounding.
+template <class real, int RULE = -1>
+DFW_HD void recon_gauss_adj(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, const real* lv,
+                            const real* ld, real* lQ, real& la_c, real* v, real* d) {
+  const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
+  const real dl = real(0.28867513459481288225);  // sqrt(3)/6
+  // reverse of the even/odd split (linear, so it needs no forward value)
+  const real lev = lv[0] + lv[1], lod = lv[1] - lv[0], levd = ld[0] + ld[1], lodd = ld[1] - ld[0];
+  real lD1 = dl * lod + levd;
+  real lD2 = real(2) * dl * lodd;
+  real lD3 = dl * real(1.0 / 12.0) * lod + real(0.25) * levd;
+  real lD4 = -real(1.0 / 180.0) * lev + dl * real(1.0 / 3.0) * lodd;
+  lQ[2] += lev;
+  real D1, D2, D3 = real(0), D4 = real(0);
+  if (df_switch<RULE>(a_lo, a_c, a_hi, k)) {
+    const real h1 = real(0.5) * (Q3 - Q1), h2 = real(0.5) * (Q1 - real(2) * Q2 + Q3);
+    D1 = a_c * h1;
+    D2 = a_c * h2;
+    la_c += lD1 * h1 + lD2 * h2;
+    const real m1 = real(0.5) * a_c * lD1, m2 = real(0.5) * a_c * lD2;
+    lQ[1] += m2 - m1;
+    lQ[2] -= real(2) * m2;
+    lQ[3] += m1 + m2;
+  } else {
+    const WenoTerms<real> T = weno_terms(Q);
+    const real b0 = T.b[0], b1 = T.b[1], b2 = T.b[2], b3 = T.b[3];
+    const real tau = (fabs(b3 - b0) + fabs(b3 - b1) + fabs(b3 - b2)) * real(1.0 / 3.0);
+    const real B0 = b0 + k.eps, B1 = b1 + k.eps, B2 = b2 + k.eps, B3 = b3 + k.eps;
+    const real P01 = B0 * B1, P23 = B2 * B3, iP = rcp_pos(P01 * P23);
+    const real a23 = P23 * iP, a01 = P01 * iP;
+    const real ib[4] = {a23 * B1, a23 * B0, a01 * B3, a01 * B2};  // 1 / B_q
+    real r[4], w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = tau * ib[q];
+      w[q] = k.d[q] * (real(1) + r[q] * r[q]);
+    }
+    const real iws = rcp_pos(w[0] + w[1] + w[2] + w[3]);
+    const real g3 = w[3] * iws;
+    const real g0 = w[0] * iws - g3 * k.dr[0];
+    const real g1 = w[1] * iws - g3 * k.dr[1];
+    const real g2 = w[2] * iws - g3 * k.dr[2];
+    const real h3 = g3 * k.inv_d3;
+    const real q1 = T.u1 - real(0.15) * T.u3, q2 = T.u2 - real(3.0 / 14.0) * T.u4;
+    D1 = real(0.5) * (g0 * T.s0 - g1 * T.s1 - g2 * T.s2) + h3 * q1;
+    D2 = real(0.5) * (g0 * T.t0 + g1 * T.t1 + g2 * T.t2) + h3 * q2;
+    D3 = h3 * T.u3;
+    D4 = h3 * T.u4;
+    // D1..D4 -> weights and terms
+    const real lg0 = real(0.5) * (lD1 * T.s0 + lD2 * T.t0);
+    const real lg1 = real(0.5) * (lD2 * T.t1 - lD1 * T.s1);
+    const real lg2 = real(0.5) * (lD2 * T.t2 - lD1 * T.s2);
+    const real lh3 = lD1 * q1 + lD2 * q2 + lD3 * T.u3 + lD4 * T.u4;
+    real ls0 = real(0.5) * g0 * lD1, ls1 = -real(0.5) * g1 * lD1, ls2 = -real(0.5) * g2 * lD1;
+    real lt0 = real(0.5) * g0 * lD2, lt1 = real(0.5) * g1 * lD2, lt2 = real(0.5) * g2 * lD2;
+    real lu1 = h3 * lD1, lu2 = h3 * lD2;
+    real lu3 = h3 * (lD3 - real(0.15) * lD1), lu4 = h3 * (lD4 - real(3.0 / 14.0) * lD2);
+    // weights -> indicators
+    const real lg3 = lh3 * k.inv_d3 - lg0 * k.dr[0] - lg1 * k.dr[1] - lg2 * k.dr[2];
+    const real lgs[4] = {lg0, lg1, lg2, lg3};
+    const real lS = -(lg0 * w[0] + lg1 * w[1] + lg2 * w[2] + lg3 * w[3]) * iws * iws;
+    real ltau = real(0), lb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const real lr = (lgs[q] * iws + lS) * k.d[q] * real(2) * r[q];
+      ltau += lr * ib[q];
+      lb[q] = -lr * r[q] * ib[q];
+    }
+    const real s30 = sgn(b3 - b0), s31 = sgn(b3 - b1), s32 = sgn(b3 - b2);
+    const real lt3 = ltau * real(1.0 / 3.0);
+    lb[3] += lt3 * (s30 + s31 + s32);
+    lb[0] -= lt3 * s30;
+    lb[1] -= lt3 * s31;
+    lb[2] -= lt3 * s32;
+    // indicators -> terms
+    const real k1312 = real(13.0 / 12.0), k14 = real(0.25);
+    lt0 += real(2) * k1312 * T.t0 * lb[0];
+    ls0 += real(2) * k14 * T.s0 * lb[0];
+    lt1 += real(2) * k1312 * T.t1 * lb[1];
+    ls1 += real(2) * k14 * T.s1 * lb[1];
+    lt2 += real(2) * k1312 * T.t2 * lb[2];
+    ls2 += real(2) * k14 * T.s2 * lb[2];
+    const real e1 = T.u1 + real(0.1) * T.u3, e2 = T.u2 + real(123.0 / 455.0) * T.u4;
+    const real le1 = real(2) * e1 * lb[3], le2 = real(26.0 / 3.0) * e2 * lb[3];
+    lu1 += le1;
+    lu2 += le2;
+    lu3 += real(781.0 / 10.0) * T.u3 * lb[3] + real(0.1) * le1;
+    lu4 += real(2.0 * 1421461.0 / 2275.0) * T.u4 * lb[3] + real(123.0 / 455.0) * le2;
+    // terms -> averages: u1 = (-11 d40 - 82 s1)/120, u2 = (34 t1 - 3 (t0 + t2))/56,
+    // u3 = (2 s1 + d40)/12, u4 = (t0 - 2 t1 + t2)/24, d40 = Q4 - Q0, s2 = t2 - 2 (Q3 - Q2)
+    const real ld40 = -real(11.0 / 120.0) * lu1 + real(1.0 / 12.0) * lu3;
+    ls1 += -real(82.0 / 120.0) * lu1 + real(2.0 / 12.0) * lu3;
+    lt1 += real(34.0 / 56.0) * lu2 - real(2.0 / 24.0) * lu4;
+    lt0 += -real(3.0 / 56.0) * lu2 + real(1.0 / 24.0) * lu4;
+    lt2 += -real(3.0 / 56.0) * lu2 + real(1.0 / 24.0) * lu4 + ls2;
+    lQ[0] += lt0 + ls0 - ld40;
+    lQ[1] += -real(2) * lt0 + lt1 - real(4) * ls0 + ls1;
+    lQ[2] += lt0 - real(2) * lt1 + lt2 + real(3) * ls0 + real(2) * ls2;
+    lQ[3] += lt1 - real(2) * lt2 - ls1 - real(2) * ls2;
+    lQ[4] += lt2 + ld40;
+  }
+  (void)Q0;
+  (void)Q4;
+  const real ev = Q2 - real(1.0 / 180.0) * D4, od = dl * (D1 + real(1.0 / 12.0) * D3);
+  const real evd = D1 + real(0.25) * D3, odd = dl * (real(2) * D2 + real(1.0 / 3.0) * D4);
+  v[0] = ev - od;
+  v[1] = ev + od;
+  d[0] = evd - odd;
+  d[1] = evd + odd;
+}
+
 template <class real>
 DFW_HD void eval_poly_at_adj(real xi, real lval, real lder, real* lP) {
   real x2 = xi * xi, x3 = x2 * xi, x4 = x3 * xi;
@@ -1106,17 +1219,14 @@ DFW_HD void segment_side(const Basis<real>& B, LineFn line, const real* al, real
   real qv[2][4], qd[2][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    real s[5], Pc[5];
+    real s[5], v[2], d[2];
 #pragma unroll
     for (int m = 0; m < 5; ++m) s[m] = Q[m][c];
-    recon_poly<real, 5, RULE>(s, al[0], al[1], al[2], k, Pc);
-    real v0, d0, v1, d1;
-    eval_poly_at(Pc, real(kXiGp0), v0, d0);
-    eval_poly_at(Pc, real(kXiGp1), v1, d1);
-    qv[0][c] = v0;
-    qv[1][c] = v1;
-    qd[0][c] = d0 * inv_dt;
-    qd[1][c] = d1 * inv_dt;
+    recon_gauss<real, RULE>(s, al[0], al[1], al[2], k, v, d);
+    qv[0][c] = v[0];
+    qv[1][c] = v[1];
+    qd[0][c] = d[0] * inv_dt;
+    qd[1][c] = d[1] * inv_dt;
   }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
@@ -1132,7 +1242,7 @@ template <int C, int RULE, class real, class LineFn, class AddFn>
 DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
                                   const real (*lgw)[4], const real (*lgwt)[4], real lqv0, real lqv1, real lqd0,
                                   real lqd1, AddFn ll_add, BasisAdj<real>& lB, real& la_c) {
-  real s[5], Pc[5], lP[5] = {0, 0, 0, 0, 0}, lQc[5] = {0, 0, 0, 0, 0};
+  real s[5], lQc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     real w[4];
@@ -1140,16 +1250,13 @@ DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real*
     for (int c = 0; c < 4; ++c) w[c] = line(m, c);
     s[m] = project_comp<C>(B, w);
   }
-  eval_poly_at_adj(real(kXiGp0), lqv0, lqd0 * inv_dt, lP);
-  eval_poly_at_adj(real(kXiGp1), lqv1, lqd1 * inv_dt, lP);
-  recon_poly_adj<real, 5, RULE>(s, al[0], al[1], al[2], k, lP, lQc, la_c, Pc);
-  real v0, d0, v1, d1;
-  eval_poly_at(Pc, real(kXiGp0), v0, d0);
-  eval_poly_at(Pc, real(kXiGp1), v1, d1);
-  unproject_adj_B_comp<C>(B, v0, lgw[0], lB);
-  unproject_adj_B_comp<C>(B, v1, lgw[1], lB);
-  unproject_adj_B_comp<C>(B, d0 * inv_dt, lgwt[0], lB);
-  unproject_adj_B_comp<C>(B, d1 * inv_dt, lgwt[1], lB);
+  const real lv[2] = {lqv0, lqv1}, ld[2] = {lqd0 * inv_dt, lqd1 * inv_dt};
+  real v[2], d[2];
+  recon_gauss_adj<real, RULE>(s, al[0], al[1], al[2], k, lv, ld, lQc, la_c, v, d);
+  unproject_adj_B_comp<C>(B, v[0], lgw[0], lB);
+  unproject_adj_B_comp<C>(B, v[1], lgw[1], lB);
+  unproject_adj_B_comp<C>(B, d[0] * inv_dt, lgwt[0], lB);
+  unproject_adj_B_comp<C>(B, d[1] * inv_dt, lgwt[1], lB);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     real w[4];

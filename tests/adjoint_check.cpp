@@ -126,6 +126,19 @@ int main() {
         recon_poly_adj<real, 2>(xx, alo, xx[5], ahi, k, l, lx, lx[5]);
       };
       check(branch ? "recon2_df" : "recon2_weno", x, 2, f2, a2);
+      auto fg = [&](const double* xx, double* y) {
+        real v[2], d[2];
+        recon_gauss<real>(xx, alo, xx[5], ahi, k, v, d);
+        y[0] = v[0];
+        y[1] = v[1];
+        y[2] = d[0];
+        y[3] = d[1];
+      };
+      auto ag = [&](const double* xx, const double* l, double* lx) {
+        real v[2], d[2];
+        recon_gauss_adj<real>(xx, alo, xx[5], ahi, k, l, l + 2, lx, lx[5], v, d);
+      };
+      check(branch ? "recon_gauss_df" : "recon_gauss_weno", x, 4, fg, ag);
     }
     // ---- prim + DF
     {

@@ -23,7 +23,8 @@ def lines(tmp_path_factory):
 
 def test_every_adjoint_matches_central_differences(lines):
     names = {ln[0] for ln in lines}
-    for need in ("project", "unproject", "recon5_weno", "recon5_df", "recon2_weno", "recon2_df", "df_factor",
+    for need in ("project", "unproject", "recon5_weno", "recon5_df", "recon2_weno", "recon2_df", "recon_gauss_weno",
+                 "recon_gauss_df", "df_factor",
                  "lf_flux", "gks_flux", "gks_flux_tau0", "normal_sweep", "normal_sweep_df", "segment_lf",
                  "segment_lf_df", "segment_gks", "segment_gks_df", "normal_side_fwd", "normal_side_fwd_df"):
         assert need in names, need
