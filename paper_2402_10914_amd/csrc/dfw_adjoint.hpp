@@ -361,8 +361,8 @@ DFW_HD void recon_poly_adj(const real* Q, real a_lo, real a_c, real a_hi, const 
 template <class real, int RULE = -1>
 DFW_HD void recon_gauss_adj(const real* Q, real a_lo, real a_c, real a_hi, const Coef<real>& k, const real* lv,
                             const real* ld, real* lQ, real& la_c, real* v, real* d) {
-  const real Q0 = Q[0], Q1 = Q[1], Q2 = Q[2], Q3 = Q[3], Q4 = Q[4];
-  const real dl = real(0.28867513459481288225);  // sqrt(3)/6
+  const real Q1 = Q[1], Q2 = Q[2], Q3 = Q[3];
+  const real dl = real(kGpDelta);
   // reverse of the even/odd split (linear, so it needs no forward value)
   const real lev = lv[0] + lv[1], lod = lv[1] - lv[0], levd = ld[0] + ld[1], lodd = ld[1] - ld[0];
   real lD1 = dl * lod + levd;
@@ -458,24 +458,12 @@ DFW_HD void recon_gauss_adj(const real* Q, real a_lo, real a_c, real a_hi, const
     lQ[3] += lt1 - real(2) * lt2 - ls1 - real(2) * ls2;
     lQ[4] += lt2 + ld40;
   }
-  (void)Q0;
-  (void)Q4;
   const real ev = Q2 - real(1.0 / 180.0) * D4, od = dl * (D1 + real(1.0 / 12.0) * D3);
   const real evd = D1 + real(0.25) * D3, odd = dl * (real(2) * D2 + real(1.0 / 3.0) * D4);
   v[0] = ev - od;
   v[1] = ev + od;
   d[0] = evd - odd;
   d[1] = evd + odd;
-}
-
-template <class real>
-DFW_HD void eval_poly_at_adj(real xi, real lval, real lder, real* lP) {
-  real x2 = xi * xi, x3 = x2 * xi, x4 = x3 * xi;
-  lP[0] += lval;
-  lP[1] += lval * xi + lder;
-  lP[2] += lval * x2 + lder * real(2) * xi;
-  lP[3] += lval * x3 + lder * real(3) * x2;
-  lP[4] += lval * x4 + lder * real(4) * x3;
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -103,7 +103,7 @@ DFW_HD Basis<real> make_basis(const real* wa, const real* wb, const Coef<real>& 
   B.c = sqrt(c2);
   B.ic = real(1) / B.c;
   B.H = (e + p) * ir;
-  B.b1 = k.gm1 / c2;
+  B.b1 = k.gm1 * (B.ic * B.ic);  // (gamma - 1) / c^2 from the reciprocal already formed
   B.b2 = B.hq2 * B.b1;
   return B;
 }
@@ -315,20 +315,14 @@ DFW_HD void recon_poly(const real* Q, real a_lo, real a_c, real a_hi, const Coef
   if (NDEG > 4) P[4] = P4;
 }
 
-// Gauss points of a segment [-1, 0] (in units of its length): -1/2 -+ sqrt(3)/6.
-constexpr double kXiGp0 = -0.5 - 0.28867513459481288225;
-constexpr double kXiGp1 = -0.5 + 0.28867513459481288225;
-
-template <class real>
-DFW_HD void eval_poly_at(const real* P, real xi, real& val, real& der) {
-  val = (((P[4] * xi + P[3]) * xi + P[2]) * xi + P[1]) * xi + P[0];
-  der = ((real(4) * P[4] * xi + real(3) * P[3]) * xi + real(2) * P[2]) * xi + P[1];
-}
+// Gauss points of a segment [-1, 0] (in units of its length): -1/2 -+ kGpDelta, kGpDelta = sqrt(3)/6.
+constexpr double kGpDelta = 0.28867513459481288225;
 
 // The hybrid reconstruction of one cell evaluated at the two Gauss points of the segment, xi =
-// kXiGp0, kXiGp1 (the tangential sweep): values v[g] and slopes d[g] (per unit xi).  The same
-// polynomial as recon_poly, taken in the centred variable zeta = xi + 1/2, where the Gauss points
-// are zeta = -/+ delta with delta^2 = 1/12:  P = D0 + D1 zeta + ... + D4 zeta^4 with
+// -1/2 - kGpDelta and -1/2 + kGpDelta (the tangential sweep): values v[g] and slopes d[g] (per
+// unit xi).  The same polynomial as recon_poly, taken in the centred variable zeta = xi + 1/2,
+// where the Gauss points are zeta = -/+ delta, delta = kGpDelta, delta^2 = 1/12:
+//   P = D0 + D1 zeta + ... + D4 zeta^4 with
 //   D1 = (g0 s0 - g1 s1 - g2 s2)/2 + h3 (u1 - 3/20 u3),  D2 = (g0 t0 + g1 t1 + g2 t2)/2 + h3 (u2 - 3/14 u4),
 //   D3 = h3 u3,  D4 = h3 u4,
 // and D0 fixed by the cell mean (D0 = Q_i - D2/12 - D4/80), so that
@@ -371,7 +365,7 @@ DFW_HD void recon_gauss(const real* Q, real a_lo, real a_c, real a_hi, const Coe
     D3 = h3 * T.u3;
     D4 = h3 * T.u4;
   }
-  const real dl = real(0.28867513459481288225);  // sqrt(3)/6
+  const real dl = real(kGpDelta);
   const real ev = Q2 - real(1.0 / 180.0) * D4, od = dl * (D1 + real(1.0 / 12.0) * D3);
   const real evd = D1 + real(0.25) * D3, odd = dl * (real(2) * D2 + real(1.0 / 3.0) * D4);
   v[0] = ev - od;
