@@ -33,8 +33,12 @@ namespace dfw {
 // ------------------------------------------------------------------------------------------------
 // Device-side descriptions.
 // ------------------------------------------------------------------------------------------------
+constexpr int kSpeedSlots = 64;  // one wavefront: the slots of a bank are reduced by one wave
 struct Ctrl {
-  unsigned long long smax_bits[2];  // running max signal speed / dx for the next step (ping-pong)
+  // running max signal speed / dx for the next step (ping-pong banks).  Workgroup b adds its
+  // maximum to slot b % kSpeedSlots of the bank, so that the atomics of a launch spread over
+  // kSpeedSlots addresses instead of serialising on one; readers take the max over the slots.
+  unsigned long long smax_bits[2][kSpeedSlots];
   double dt;                        // dt of the current step; 0 when the step is skipped (t_end reached)
   double t;                         // accumulated time (advanced by the last kernel of a step)
   int fail_at;                      // steps completed when a non-physical state was first met,
@@ -42,6 +46,18 @@ struct Ctrl {
   int pad[3];
 };
 constexpr int kNoFail = 0x7fffffff;
+
+// Max over the slots of one bank (the bit patterns of non-negative doubles order as the values),
+// taken by a whole wavefront: lane l reads slot l.  Every lane of the wave must be active.
+__device__ __forceinline__ double bank_max(const Ctrl* ctrl, int bank) {
+  double v = __longlong_as_double((long long)ctrl->smax_bits[bank][threadIdx.x & (kSpeedSlots - 1)]);
+#pragma unroll
+  for (int off = kSpeedSlots / 2; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
 
 // One grid: sizes, spacing, boundaries and element offsets of its arrays inside the (packed) state,
 // alpha, stage and interface buffers.
@@ -169,7 +185,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   // t_end > 0 the step that would pass t_end ends on it, and later steps are skipped (dt = 0).
   double dtd;
   if (lead) {
-    dtd = dt_host > 0.0 ? dt_host : S.cfl / __longlong_as_double((long long)ctrl->smax_bits[step & 1]);
+    dtd = dt_host > 0.0 ? dt_host : S.cfl / bank_max(ctrl, step & 1);
     if (S.t_end > 0.0) {
       const double rem = S.t_end - ctrl->t;
       if (dtd >= rem) dtd = rem > 0.0 ? rem : 0.0;
@@ -177,10 +193,12 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   } else {
     dtd = dt_host > 0.0 ? dt_host : ctrl->dt;
   }
-  if (lead && lead_tile && tid == 0) {
-    ctrl->dt = dtd;
-    if (dtd > 0.0) ctrl->smax_bits[(step + 1) & 1] = 0ull;
-    if (dt_hist) dt_hist[(size_t)gi * nsteps + step] = dtd;
+  if (lead && lead_tile) {
+    if (dtd > 0.0 && tid < kSpeedSlots) ctrl->smax_bits[(step + 1) & 1][tid] = 0ull;
+    if (tid == 0) {
+      ctrl->dt = dtd;
+      if (dt_hist) dt_hist[(size_t)gi * nsteps + step] = dtd;
+    }
   }
   if (!(dtd > 0.0)) return;  // uniform over the launch
   const real dt = real(dtd);
@@ -441,7 +459,8 @@ __device__ __forceinline__ void block_reduce_commit(double s, int bad, Ctrl* ctr
       s = red[q] > s ? red[q] : s;
       bad |= redb[q];
     }
-    if (s > 0.0) atomicMax(&ctrl->smax_bits[slot], (unsigned long long)__double_as_longlong(s));
+    if (s > 0.0)
+      atomicMax(&ctrl->smax_bits[slot][blockIdx.x & (kSpeedSlots - 1)], (unsigned long long)__double_as_longlong(s));
     if (bad) atomicMin(&ctrl->fail_at, step_done);
   }
 }
@@ -587,8 +606,7 @@ __global__ void k_ctrl_init(Ctrl* ctrls, int n) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   Ctrl* c = ctrls + g;
-  c->smax_bits[0] = 0ull;
-  c->smax_bits[1] = 0ull;
+  for (int q = 0; q < kSpeedSlots; ++q) c->smax_bits[0][q] = c->smax_bits[1][q] = 0ull;
   c->dt = 0.0;
   c->t = 0.0;
   c->fail_at = kNoFail;
@@ -1074,8 +1092,10 @@ dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* 
   Ctrl h;
   HIP_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  unsigned long long bits = 0ull;
+  for (int q = 0; q < kSpeedSlots; ++q) bits = h.smax_bits[0][q] > bits ? h.smax_bits[0][q] : bits;
   double v;
-  std::memcpy(&v, &h.smax_bits[0], sizeof(double));
+  std::memcpy(&v, &bits, sizeof(double));
   if (smax) *smax = v;
   if (nonphys) *nonphys = h.fail_at != kNoFail ? 1 : 0;
   return DFW_OK;
