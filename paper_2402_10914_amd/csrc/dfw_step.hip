@@ -436,10 +436,10 @@ __device__ __forceinline__ bool cell_speed(const real* w, const Scheme& S, const
   return ok;
 }
 
-// Workgroup max of a non-negative double and OR of a flag, then one atomic each.  A flag records
-// step_done as the failing step; it stops the kernels of later steps only, so every workgroup of
-// the launch that finds it still writes its cells and the stored state does not depend on the
-// order in which workgroups run.
+// Workgroup max of a non-negative double and OR of a flag, then one atomic each (the max into the
+// workgroup's slot of the bank).  A flag records step_done as the failing step; it stops the
+// kernels of later steps only, so every workgroup of the launch that finds it still writes its
+// cells and the stored state does not depend on the order in which workgroups run.
 __device__ __forceinline__ void block_reduce_commit(double s, int bad, Ctrl* ctrl, int slot, int step_done) {
   __shared__ double red[kCellBlock / 64];
   __shared__ int redb[kCellBlock / 64];
