@@ -289,7 +289,10 @@ def main():
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 4),
                     "traffic": load_traffic(f"traffic_faces1_{args.workload}.json"),
-                    "kernel": "k_faces (first stage)", "flops_per_launch": fl, "avg_launch_us": round(avg_s * 1e6, 2)}
+                    "kernel": "k_faces (first stage)", "flops_per_launch": fl, "avg_launch_us": round(avg_s * 1e6, 2),
+                    "flops_counted": "arithmetic the kernel executes: adds, multiplies, divides, sqrt, exp, erfc "
+                                     "of its own device functions counted on the host, operations the compiler "
+                                     "folds excluded"}
         print(f"# faces1 avg {avg_s * 1e6:.1f} us -> {achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
 
     hbm = BYTES_PER_CELL_UPDATE[esize] * value / 1e9
