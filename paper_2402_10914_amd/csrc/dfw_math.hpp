@@ -15,8 +15,8 @@
 
 namespace dfw {
 
-// Reciprocal of a positive, finite, normal number (the WENO-Z denominators: each is at least
-// eps^2).  On the device: the hardware reciprocal estimate refined by Newton-Raphson steps in fused
+// Reciprocal of a positive, finite, normal number (the WENO-Z denominators: products of the
+// b_k + eps, at least eps^4, and sums of positive weights).  On the device: the hardware reciprocal estimate refined by Newton-Raphson steps in fused
 // form, e = 1 - x r, r <- r + r e (two steps in FP64, one in FP32), within one unit in the last
 // place of 1/x, in 5 (FP64) or 3 (FP32) instructions instead of the ten-instruction IEEE division
 // sequence, whose scaling and fix-up steps only matter for zero, infinite or subnormal operands.
