@@ -308,6 +308,65 @@ def test_gks_uniform_and_smooth_limits(c1, c2):
         np.testing.assert_allclose(Ft, Ft_ck, rtol=1e-6, atol=1e-6)
 
 
+def _pressure(W, g=GAMMA):
+    return (g - 1) * (W[3] - 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0])
+
+
+def _gks_pair(rng):
+    """Two random states with clearly different pressures, and random slopes on both sides."""
+    while True:
+        Wl, Wr = _rand_state(rng), _rand_state(rng)
+        pl, pr = _pressure(Wl), _pressure(Wr)
+        if abs(pl - pr) > 0.2 * (pl + pr):
+            break
+    sl = [rng.normal(size=4) * 0.3 for _ in range(4)]
+    return Wl, Wr, sl
+
+
+def test_gks_collision_time_scales_with_dt():
+    """Section 2.2: tau_n = c1 dt + c2 |(pl - pr)/(pl + pr)| dt is proportional to dt, and tau_n
+    enters only as exp(-t / tau_n) (reading R7).  Every other time dependence of the interface
+    distribution pairs t with a slope, so the flux is invariant when dt is scaled by s and the
+    slopes by 1/s: F^n is unchanged and dt * dF/dt is unchanged.  An additive term in tau_n
+    without dt (in either the c1 or the c2 part) breaks the invariance."""
+    rng = np.random.default_rng(2402)
+    for _ in range(4):
+        Wl, Wr, (Wlx, Wly, Wrx, Wry) = _gks_pair(rng)
+        dt = 2e-3
+        F0, Ft0 = O.flux_gp(O.FLUX_GKS, Wl, Wlx, Wly, Wr, Wrx, Wry, dt=dt, c1=0.01, c2=5.0)
+        for s in (0.25, 4.0):
+            F1, Ft1 = O.flux_gp(O.FLUX_GKS, Wl, Wlx / s, Wly / s, Wr, Wrx / s, Wry / s, dt=s * dt, c1=0.01, c2=5.0)
+            np.testing.assert_allclose(F1, F0, rtol=1e-12, atol=1e-12 * np.abs(F0).max())
+            np.testing.assert_allclose(s * Ft1, Ft0, rtol=1e-9, atol=1e-9 * np.abs(Ft0).max())
+
+
+def test_gks_collision_time_pressure_jump_term():
+    """Section 2.2, the pressure-jump part of tau_n: with equal pressures on both sides it vanishes
+    (the flux does not depend on c2); otherwise (c1 = 0, c2 = x) is the same collision time as
+    (c1 = x |pl - pr| / (pl + pr), c2 = 0), with pressures from the equation of state."""
+    rng = np.random.default_rng(77)
+    for _ in range(4):
+        Wl, Wr, (Wlx, Wly, Wrx, Wry) = _gks_pair(rng)
+        dt = 1e-3
+        # equal pressures: the right state moved to the left state's pressure
+        r, u, v = Wr[0], Wr[1] / Wr[0], Wr[2] / Wr[0]
+        We = np.array([r, r * u, r * v, _pressure(Wl) / (GAMMA - 1) + 0.5 * r * (u * u + v * v)])
+        Fa, Fta = O.flux_gp(O.FLUX_GKS, Wl, Wlx, Wly, We, Wrx, Wry, dt=dt, c1=0.01, c2=0.0)
+        Fb, Ftb = O.flux_gp(O.FLUX_GKS, Wl, Wlx, Wly, We, Wrx, Wry, dt=dt, c1=0.01, c2=50.0)
+        np.testing.assert_allclose(Fb, Fa, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(Ftb, Fta, rtol=1e-9, atol=1e-9 * np.abs(Fta).max())
+        # the two ways of writing the same collision time
+        x = 3.0
+        jump = abs(_pressure(Wl) - _pressure(Wr)) / (_pressure(Wl) + _pressure(Wr))
+        Fc, Ftc = O.flux_gp(O.FLUX_GKS, Wl, Wlx, Wly, Wr, Wrx, Wry, dt=dt, c1=0.0, c2=x)
+        Fd, Ftd = O.flux_gp(O.FLUX_GKS, Wl, Wlx, Wly, Wr, Wrx, Wry, dt=dt, c1=x * jump, c2=0.0)
+        np.testing.assert_allclose(Fd, Fc, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(Ftd, Ftc, rtol=1e-9, atol=1e-9 * np.abs(Ftc).max())
+        # and the jump term does act: a tenfold c2 changes the flux
+        Fe, _ = O.flux_gp(O.FLUX_GKS, Wl, Wlx, Wly, Wr, Wrx, Wry, dt=dt, c1=0.0, c2=10 * x)
+        assert np.abs(Fe - Fc).max() > 1e-8 * np.abs(Fc).max()
+
+
 def test_gks_first_order_flux_is_kinetic_flux_vector_splitting_limit():
     """With tau_n -> infinity relative to dt the GKS flux tends to the collisionless (free
     transport) flux of the two half Maxwellians, the kinetic flux-vector splitting."""
@@ -331,6 +390,106 @@ def test_gks_first_order_flux_is_kinetic_flux_vector_splitting_limit():
     ref, _ = integrate.quad(lambda u: rho * u * math.sqrt(lam / math.pi) * math.exp(-lam * (u - U) ** 2),
                             0, np.inf, epsabs=1e-14)
     assert m(Wl, 1, 1, 0, 0) == pytest.approx(ref, rel=1e-10)
+
+
+# ----------------------------------------------------------------------------------------------
+# Worked examples of eqs. (36)-(39) in exact rational arithmetic (the global indicator of eq. (37))
+# ----------------------------------------------------------------------------------------------
+
+def _exact_candidates(Q):
+    """Coefficients of p0..p3 (in xi) from the printed multipliers, exactly, for exact Q."""
+    g = _gold("weno_ao_candidates.json")
+    out = []
+    for name in ("p0", "p1", "p2", "p3"):
+        out.append([sum((Fraction(s) * q for s, q in zip(g[name]["x%d" % n], Q)), Fraction(0))
+                    if "x%d" % n in g[name] else Fraction(0) for n in range(5)])
+    return out
+
+
+def _exact_betas(Q):
+    """eq. (38) exactly: Jiang-Shu forms for the quadratics; for the quartic the integral over the
+    cell [-1, 0] of the squared derivatives of orders 1..4, through exact antiderivatives."""
+    a, b, c, d, e = Q
+    js = [Fraction(13, 12) * (a - 2 * b + c) ** 2 + Fraction(1, 4) * (a - 4 * b + 3 * c) ** 2,
+          Fraction(13, 12) * (b - 2 * c + d) ** 2 + Fraction(1, 4) * (b - d) ** 2,
+          Fraction(13, 12) * (c - 2 * d + e) ** 2 + Fraction(1, 4) * (3 * c - 4 * d + e) ** 2]
+    p3 = _exact_candidates(Q)[3]
+    tot = Fraction(0)
+    der = list(p3)
+    for _ in range(4):
+        der = [der[n + 1] * (n + 1) for n in range(len(der) - 1)]
+        sq = [Fraction(0)] * (2 * len(der) - 1)
+        for i, x in enumerate(der):
+            for j, y in enumerate(der):
+                sq[i + j] += x * y
+        # int_{-1}^{0} xi^m dxi = -(-1)^(m+1) / (m+1)
+        tot += sum(cm * (-Fraction(-1) ** (m + 1)) / (m + 1) for m, cm in enumerate(sq))
+    return js + [tot]
+
+
+def _linear_weights(d_h, d_l):
+    dH, dL = Fraction(d_h), Fraction(d_l)
+    d0 = (1 - dH) * (1 - dL) / 2
+    return [d0, (1 - dH) * dL, d0, dH]
+
+
+def _exact_weno_z(Q, d_h=0.85, d_l=0.85, eps=1e-6, tau_factor=Fraction(1, 3)):
+    """Section 3.1 worked through by hand in exact fractions: tau_Z of eq. (37) is the mean of
+    |beta3 - beta_k| over k = 0, 1, 2 (tau_factor 1/3), eq. (36) weights, eq. (39) combination
+    P = sum_{k<3} w_k p_k + w_3 (p3 - sum_{k<3} d_k p_k) / d_3."""
+    Q = [Fraction(q) for q in Q]
+    p = _exact_candidates(Q)
+    beta = _exact_betas(Q)
+    d = _linear_weights(d_h, d_l)
+    ep = Fraction(eps)
+    tau = tau_factor * sum(abs(beta[3] - beta[k]) for k in range(3))
+    w = [d[k] * (1 + (tau / (beta[k] + ep)) ** 2) for k in range(4)]
+    s = sum(w)
+    wb = [x / s for x in w]
+    return [sum(wb[k] * p[k][n] for k in range(3)) + wb[3] * (p[3][n] - sum(d[k] * p[k][n] for k in range(3))) / d[3]
+            for n in range(5)]
+
+
+# rational stencils with indicators of order one (so that eps does not hide tau_Z) and distinct
+# indicators (so that every weight moves with tau_Z)
+_WORKED_STENCILS = [[1, 2, 4, 3, 7], [0.5, -1.25, 2.0, 0.75, -0.5], [3, 3.5, 1, -2, 0.25]]
+
+
+@pytest.mark.parametrize("Q", _WORKED_STENCILS)
+def test_weno_z_weights_worked_example_exact(Q):
+    """WENO-AO(5,3) with WENO-Z weights (eqs. (36)-(39)) against the same reconstruction worked out in
+    exact rational arithmetic from the printed candidates.  The global indicator of eq. (37) is the
+    mean of the three differences; a factor of 3 in it moves P by far more than the tolerance."""
+    prm = O.make_params()
+    got = O.weno_ao(np.array(Q, dtype=float), prm)
+    want = [float(x) for x in _exact_weno_z(Q)]
+    scale = max(abs(x) for x in want)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * scale)
+    alt = [float(x) for x in _exact_weno_z(Q, tau_factor=Fraction(1))]
+    assert max(abs(a - b) for a, b in zip(alt, want)) > 1e-4 * scale
+
+
+def _exact_limiter_weight(Q, eps=1e-6, tau_factor=Fraction(1, 3)):
+    """eq. (29) worked out exactly: a1 = 1 + (tau_Z / (beta_min + eps))^2, a2 = 1 + (tau_Z / (beta_max
+    + eps))^2, weight = 2 a2 / (a1 + a2), beta over the four indicators, tau_Z of eq. (37)."""
+    Q = [Fraction(q) for q in Q]
+    beta = _exact_betas(Q)
+    tau = tau_factor * sum(abs(beta[3] - beta[k]) for k in range(3))
+    ep = Fraction(eps)
+    a1 = 1 + (tau / (min(beta) + ep)) ** 2
+    a2 = 1 + (tau / (max(beta) + ep)) ** 2
+    return 2 * a2 / (a1 + a2)
+
+
+@pytest.mark.parametrize("Q", _WORKED_STENCILS)
+def test_limiter_weight_worked_example_exact(Q):
+    """The time-limiter weight of eq. (29) (reading: extremes over the four indicators) against exact
+    rational arithmetic; a factor of 3 in tau_Z of eq. (37) changes it by far more than the tolerance."""
+    got = O.limiter_weight(np.array(Q, dtype=float), O.make_params())
+    want = float(_exact_limiter_weight(Q))
+    assert got == pytest.approx(want, rel=1e-13, abs=1e-15)
+    alt = float(_exact_limiter_weight(Q, tau_factor=Fraction(1)))
+    assert abs(alt - want) > 1e-3 * want
 
 
 # ----------------------------------------------------------------------------------------------
