@@ -144,3 +144,31 @@ def test_full_ragged_batch_equals_loop(dtype):
     assert len(failed) <= 2, failed
     if dtype == torch.float64:
         assert failed == [161] and out[161][3] == 22
+
+
+def test_failing_ragged_grid_matches_oracle_up_to_its_failure():
+    """Grid 161 of the 256-grid workload: the oracle fails after 22 steps (pinned on the CPU); the
+    GPU run equals the oracle through step 21, every cell, and fails at the same step, alone and
+    inside the batch."""
+    probs = WL.batch(256, seed=256, flux=WL.FLUX_LF, cfl=0.4, nsteps=100)
+    p = probs[161]
+    g = O.make_grid(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y)
+    Wo, ao, _, dto, fso = O.run(p.W, p.alpha, g, O.make_params(flux=O.FLUX_LF, cfl=0.4), 21)
+    assert fso == -1
+    api = _api()
+    st = api.Stepper.for_problem(p, api.Params(flux=0, cfl=0.4))
+    W = torch.tensor(p.W, device="cuda")
+    A = torch.tensor(p.alpha, device="cuda")
+    dth = torch.zeros(21, dtype=torch.float64, device="cuda")
+    _, fs = st.run(W, A, 21, dt_hist=dth)
+    assert fs == -1
+    Wg, Ag = W.cpu().numpy(), A.cpu().numpy()
+    for c in range(4):
+        assert np.abs(Wg[c] - Wo[c]).sum() / np.abs(Wo[c]).sum() <= 1e-12
+        assert np.abs(Wg[c] - Wo[c]).max() <= 1e-11 * np.abs(Wo[c]).max()
+    assert np.abs(Ag - ao).sum() / np.abs(ao).sum() <= 1e-12
+    np.testing.assert_allclose(dth.cpu().numpy(), dto, rtol=1e-12)
+    _, fs = st.run(W, A, 79)
+    assert fs == 1  # the 22nd step fails
+    out = _batched([p, probs[160]], api.Params(flux=0, cfl=0.4), 100)
+    assert out[0][3] == 22 and out[1][3] == -1

@@ -3,7 +3,8 @@
 * 512x512 Riemann, GKS, 200 steps (the benchmark workload): the whole run against the oracle's
   stored result (tests/golden/make_riemann512.py, oracle only) at 4096 seeded cells and the two
   centre lines, plus the dt history.
-* 4096x4096 circles, LF and GKS, FP64 and FP32: one step at full size against the oracle on
+* 4096x4096 circles, LF and GKS, FP64 and FP32: the whole 50-step run against the oracle's stored
+  result (tests/golden/make_circles4096.py, oracle only); one step at full size against the oracle on
   sampled patches (the oracle computes dt from the whole grid; each patch carries a 10-cell halo,
   of which one step contaminates at most 6), five steps with a fixed dt on patches with a 36-cell
   halo, and the full 50-step run checked by properties that hold at any size (no non-physical
@@ -31,7 +32,12 @@ def _api():
 
 
 def _rel_l1_rows(a, b):
-    return max(float(np.abs(a[c] - b[c]).sum() / np.abs(b[c]).sum()) for c in range(a.shape[0]))
+    """Parity measure: the larger of the relative L1 (sum|a - b| / sum|b|, per component) and a tenth
+    of the per-cell relative maximum (max|a - b| / max|b|), max over components; a bound eps on it
+    bounds the grid-wide sum by eps and every single cell by 10 eps, so that an error confined to a
+    tile seam or a boundary row cannot hide in the sum."""
+    return max(max(float(np.abs(a[c] - b[c]).sum() / np.abs(b[c]).sum()),
+                   0.1 * float(np.abs(a[c] - b[c]).max() / np.abs(b[c]).max())) for c in range(a.shape[0]))
 
 
 @pytest.mark.skipif(not os.path.exists(GOLD), reason="golden file not generated")
@@ -49,12 +55,57 @@ def test_riemann512_gks_200_steps_against_stored_oracle():
     An = A.cpu().numpy()
     jj, ii = g["jj"], g["ii"]
     assert _rel_l1_rows(Wn[:, jj, ii], g["W_s"]) <= 1e-12
-    assert np.abs(An[jj, ii] - g["a_s"]).sum() / np.abs(g["a_s"]).sum() <= 1e-12
+    assert _rel_l1_rows(An[None, jj, ii], g["a_s"][None]) <= 1e-12
     assert _rel_l1_rows(Wn[:, 256, :], g["W_row"]) <= 1e-12
     assert _rel_l1_rows(Wn[:, :, 256], g["W_col"]) <= 1e-12
     np.testing.assert_allclose(dth.cpu().numpy(), g["dt_hist"], rtol=1e-12)
     assert abs(t - float(g["t"])) <= 1e-12 * float(g["t"])
     np.testing.assert_allclose(np.abs(Wn).sum(axis=(1, 2)), g["abs_sums"], rtol=1e-12)
+
+
+def _circles_gold(name):
+    return os.path.join(os.path.dirname(__file__), "golden", f"circles4096_{name}_50.npz")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["gks", "lf"])
+def test_circles4096_fifty_steps_against_stored_oracle(name, dtype):
+    """The whole 4096x4096 circles run (50 steps, CFL time steps, the benchmark's configuration and
+    tile) against the oracle's stored result (tests/golden/make_circles4096.py, oracle only): 4096
+    seeded cells, the 4096 cells with the largest final pressure jumps, both centre lines, the dt
+    history and the sums."""
+    path = _circles_gold(name)
+    if not os.path.exists(path):
+        pytest.skip(f"{os.path.basename(path)} not generated")
+    g = np.load(path)
+    flux = WL.FLUX_GKS if name == "gks" else WL.FLUX_LF
+    pr = _circles(flux)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, cfl=0.4), tdt)
+    W = torch.tensor(pr.W, dtype=tdt, device="cuda")
+    A = torch.tensor(pr.alpha, dtype=tdt, device="cuda")
+    dth = torch.zeros(50, dtype=torch.float64, device="cuda")
+    t, fs = st.run(W, A, 50, dt_hist=dth)
+    assert fs == -1
+    Wn = W.double().cpu().numpy()
+    An = A.double().cpu().numpy()
+    n = Wn.shape[-1]
+    errs = {"cells": _rel_l1_rows(Wn[:, g["jj"], g["ii"]], g["W_s"]),
+            "fronts": _rel_l1_rows(Wn[:, g["fj"], g["fi"]], g["W_f"]),
+            "row": _rel_l1_rows(Wn[:, n // 2, :], g["W_row"]), "col": _rel_l1_rows(Wn[:, :, n // 2], g["W_col"]),
+            "alpha cells": _rel_l1_rows(An[None, g["jj"], g["ii"]], g["a_s"][None]),
+            "alpha fronts": _rel_l1_rows(An[None, g["fj"], g["fi"]], g["a_f"][None]),
+            "alpha row": _rel_l1_rows(An[None, n // 2, :], g["a_row"][None]),
+            "alpha col": _rel_l1_rows(An[None, :, n // 2], g["a_col"][None])}
+    print(f"circles4096 {name} {dtype} 50 steps: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    np.testing.assert_allclose(dth.cpu().numpy(), g["dt_hist"], rtol=1e-12 if dtype == "f64" else 1e-5)
+    assert abs(t - float(g["t"])) <= (1e-12 if dtype == "f64" else 1e-5) * float(g["t"])
+    np.testing.assert_allclose(Wn.sum(axis=(1, 2)), g["sums"], rtol=1e-12 if dtype == "f64" else 2e-5,
+                               atol=1e-12 * np.abs(g["abs_sums"]).max())
 
 
 @functools.lru_cache(maxsize=1)
@@ -134,7 +185,9 @@ def test_circles4096_one_step_on_patches(flux, dtype):
     assert _rel_l1_rows(Wg, Wr) <= tol
     ar = np.concatenate([r[1].ravel() for r in ref])
     ag = np.concatenate([g[1].ravel() for g in got])
-    assert np.abs(ag - ar).sum() / np.abs(ar).sum() <= (1e-12 if dtype == "f64" else 1e-4)
+    print(f"circles4096 one step flux {flux} {dtype}: W {_rel_l1_rows(Wg, Wr):.3e} "
+          f"alpha {_rel_l1_rows(ag[None], ar[None]):.3e}", flush=True)
+    assert _rel_l1_rows(ag[None], ar[None]) <= tol
 
 
 @pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
@@ -156,7 +209,7 @@ def test_circles4096_five_fixed_steps_on_patches(flux):
     assert _rel_l1_rows(Wg, Wr) <= 1e-12
     ar = np.concatenate([r[1].ravel() for r in ref])
     ag = np.concatenate([g[1].ravel() for g in got])
-    assert np.abs(ag - ar).sum() / np.abs(ar).sum() <= 1e-12
+    assert _rel_l1_rows(ag[None], ar[None]) <= 1e-12
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

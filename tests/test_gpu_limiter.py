@@ -24,7 +24,12 @@ def _api():
 
 
 def _rel_l1_rows(a, b):
-    return max(float(np.abs(a[c] - b[c]).sum() / np.abs(b[c]).sum()) for c in range(a.shape[0]))
+    """Parity measure: the larger of the relative L1 (sum|a - b| / sum|b|, per component) and a tenth
+    of the per-cell relative maximum (max|a - b| / max|b|), max over components; a bound eps on it
+    bounds the grid-wide sum by eps and every single cell by 10 eps, so that an error confined to a
+    tile seam or a boundary row cannot hide in the sum."""
+    return max(max(float(np.abs(a[c] - b[c]).sum() / np.abs(b[c]).sum()),
+                   0.1 * float(np.abs(a[c] - b[c]).max() / np.abs(b[c]).max())) for c in range(a.shape[0]))
 
 
 def _gpu_run(pr, flux, nsteps, dtype=torch.float64, time_limiter=1, cfl=0.4, W0=None, A0=None):
@@ -75,7 +80,11 @@ def test_limited_run_fp32_matches_oracle(flux):
     g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
     Wo, Ao, _, _, fso = O.run(pr.W, pr.alpha, g, O.make_params(flux=flux, cfl=0.4, dt_fixed=0.0, time_limiter=1), 6)
     assert fs == -1 and fso == -1
-    assert _rel_l1_rows(W, Wo) <= 1e-5
+    # relative L1 at the FP32 bar; per cell the limited map's amplification of FP32 rounding next to
+    # the jumps (see the module docstring) allows 1e-3 of the largest magnitude
+    for c in range(4):
+        assert np.abs(W[c] - Wo[c]).sum() / np.abs(Wo[c]).sum() <= 1e-5, c
+        assert np.abs(W[c] - Wo[c]).max() <= 1e-3 * np.abs(Wo[c]).max(), c
 
 
 def test_limited_periodic_run_conserves():

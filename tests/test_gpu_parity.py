@@ -1,7 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle on small and ragged grids.
 
 Tolerance: relative L1 (sum|gpu - oracle| / sum|oracle|, per component, maximum over components)
-<= 1e-12 in FP64 and <= 1e-5 for the FP32 path against the FP64 oracle."""
+<= 1e-12 in FP64 and <= 1e-5 for the FP32 path against the FP64 oracle; beside every FP64 relative
+L1, a per-cell bound max|gpu - oracle| / max|oracle| <= 1e-11 (per component), so that an error
+confined to a tile seam, a boundary row or a single cell cannot hide in the grid-wide sum."""
 import numpy as np
 import pytest
 
@@ -11,7 +13,7 @@ from paper_2402_10914_amd import workloads as WL
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL64, TOL32 = 1e-12, 1e-5
+TOL64, TOL32, CELL64 = 1e-12, 1e-5, 1e-11
 
 
 def rel_l1(a, b):
@@ -20,6 +22,20 @@ def rel_l1(a, b):
     if a.ndim == 2:
         a, b = a[None], b[None]
     return max(float(np.abs(a[c] - b[c]).sum() / max(np.abs(b[c]).sum(), 1e-300)) for c in range(a.shape[0]))
+
+
+def rel_max(a, b):
+    """Largest single-cell error over the largest magnitude, per component, max over components."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.ndim == 2:
+        a, b = a[None], b[None]
+    return max(float(np.abs(a[c] - b[c]).max() / max(np.abs(b[c]).max(), 1e-300)) for c in range(a.shape[0]))
+
+
+def close64(a, b):
+    """FP64 parity: relative L1 and per-cell bound."""
+    return rel_l1(a, b) <= TOL64 and rel_max(a, b) <= CELL64
 
 
 def _api():
@@ -91,9 +107,14 @@ def test_rhs_parity(kind, nx, ny, flux, alpha_kind):
     st = stepper(pr, gpu_params(flux))
     L1, Lt1, a1 = st.rhs(to_dev(pr.W), to_dev(alpha), dt, want_alpha=True)
     torch.cuda.synchronize()
-    assert rel_l1(L1.cpu().numpy(), L0) <= TOL64
-    assert scaled_l1(Lt1.cpu().numpy(), Lt0, L0, dt) <= TOL64
-    assert rel_l1(a1.cpu().numpy(), a0) <= TOL64
+    L1, Lt1, a1 = L1.cpu().numpy(), Lt1.cpu().numpy(), a1.cpu().numpy()
+    assert rel_l1(L1, L0) <= TOL64 and rel_max(L1, L0) <= CELL64, (rel_l1(L1, L0), rel_max(L1, L0))
+    assert scaled_l1(Lt1, Lt0, L0, dt) <= TOL64
+    assert max(float(dt * np.abs(Lt1[c] - Lt0[c]).max() / (np.abs(L0[c]).max() + dt * np.abs(Lt0[c]).max()))
+               for c in range(4)) <= CELL64
+    if kind == "circles":  # smooth data: dL/dt is no cancellation there and meets the plain bound
+        assert close64(Lt1, Lt0), (rel_l1(Lt1, Lt0), rel_max(Lt1, Lt0))
+    assert close64(a1, a0), (rel_l1(a1, a0), rel_max(a1, a0))
 
 
 def _run_pair(pr, flux, nsteps, cfl, dtype=torch.float64, **kw):
@@ -112,8 +133,8 @@ def test_density_wave_c1_parity_and_exact_solution():
     pr = WL.density_wave(64, flux=0, cfl=0.5, nsteps=20)
     (Wo, ao, to, dto, fso), (Wg, ag, tg, dtg, fsg) = _run_pair(pr, 0, 20, 0.5)
     assert fso == -1 and fsg == -1
-    assert rel_l1(Wg, Wo) <= TOL64
-    assert rel_l1(ag, ao) <= TOL64
+    assert close64(Wg, Wo), (rel_l1(Wg, Wo), rel_max(Wg, Wo))
+    assert close64(ag, ao), (rel_l1(ag, ao), rel_max(ag, ao))
     np.testing.assert_allclose(dtg, dto, rtol=1e-14)
     assert abs(tg - to) <= 1e-14 * to
     err = np.abs(Wg[0] - WL.density_wave_avg(64, 64, t=tg)).mean()
@@ -126,8 +147,8 @@ def test_riemann_run_parity(flux, nx, ny):
     pr = WL.riemann4(nx, ny, seed=11)
     (Wo, ao, to, dto, fso), (Wg, ag, tg, dtg, fsg) = _run_pair(pr, flux, 25, 0.4)
     assert fso == -1 and fsg == -1
-    assert rel_l1(Wg, Wo) <= TOL64
-    assert rel_l1(ag, ao) <= TOL64
+    assert close64(Wg, Wo), (rel_l1(Wg, Wo), rel_max(Wg, Wo))
+    assert close64(ag, ao), (rel_l1(ag, ao), rel_max(ag, ao))
     np.testing.assert_allclose(dtg, dto, rtol=1e-12)
 
 
@@ -136,8 +157,9 @@ def test_fp32_parity(flux):
     pr = WL.riemann4(40, 40, seed=3)
     (Wo, ao, to, dto, fso), (Wg, ag, tg, dtg, fsg) = _run_pair(pr, flux, 20, 0.4, dtype=torch.float32)
     assert fsg == -1
+    print(f"fp32 flux {flux}: W rel-L1 {rel_l1(Wg, Wo):.3e} alpha rel-L1 {rel_l1(ag, ao):.3e}", flush=True)
     assert rel_l1(Wg, Wo) <= TOL32
-    assert rel_l1(ag, ao) <= 1e-4  # alpha is a product of 8 factors near discontinuities
+    assert rel_l1(ag, ao) <= TOL32
 
 
 def test_max_speed_and_nonphysical():

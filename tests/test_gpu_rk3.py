@@ -20,9 +20,14 @@ def _api():
 
 
 def _rel_l1(a, b):
+    """Parity measure: the larger of the relative L1 (sum|a - b| / sum|b|, per component) and a tenth
+    of the per-cell relative maximum (max|a - b| / max|b|), max over components; a bound eps on it
+    bounds the grid-wide sum by eps and every single cell by 10 eps, so that an error confined to a
+    tile seam or a boundary row cannot hide in the sum."""
     if a.ndim == 2:
         a, b = a[None], b[None]
-    return max(float(np.abs(a[c] - b[c]).sum() / max(np.abs(b[c]).sum(), 1e-300)) for c in range(a.shape[0]))
+    return max(max(float(np.abs(a[c] - b[c]).sum() / max(np.abs(b[c]).sum(), 1e-300)),
+                   0.1 * float(np.abs(a[c] - b[c]).max() / max(np.abs(b[c]).max(), 1e-300))) for c in range(a.shape[0]))
 
 
 def _gpu_run(pr, nsteps, dtype=torch.float64, cfl=0.4, W0=None):
@@ -69,7 +74,8 @@ def test_rk3_fp32_matches_oracle():
     Wo, Ao, _, _, fso = _oracle_run(pr, 10)
     assert fs == -1 and fso == -1
     assert _rel_l1(W, Wo) <= TOL32
-    assert _rel_l1(A, Ao) <= 1e-4  # alpha is a product of 8 factors near discontinuities
+    print(f"ssprk3 fp32: W {_rel_l1(W, Wo):.3e} alpha {_rel_l1(A, Ao):.3e}", flush=True)
+    assert _rel_l1(A, Ao) <= TOL32
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 9), (30, 1), (5, 40), (64, 3), (17, 29)])

@@ -699,6 +699,20 @@ def test_nonphysical_state_is_reported():
     assert fs == 0
 
 
+def test_ragged_batch_grid_161_fails_at_step_22():
+    """The 256-grid batch workload (seed 256, LF, CFL 0.4) holds one four-quadrant Riemann grid
+    (index 161, 60 x 170, transmissive) on which the scheme, which has no positivity limiter, meets a
+    non-physical cell average after 22 steps; the GPU batch and loop report the same step."""
+    probs = WL.batch(256, seed=256, flux=WL.FLUX_LF, cfl=0.4, nsteps=100)
+    p = probs[161]
+    assert (p.name, p.nx, p.ny, p.bc_x) == ("riemann4", 60, 170, O.BC_TRANSMISSIVE)
+    g = O.make_grid(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y)
+    _, _, _, _, fs = O.run(p.W, p.alpha, g, O.make_params(flux=O.FLUX_LF, cfl=0.4), 100)
+    assert fs == 22
+    _, _, _, _, fs21 = O.run(p.W, p.alpha, g, O.make_params(flux=O.FLUX_LF, cfl=0.4), 21)
+    assert fs21 == -1
+
+
 @pytest.mark.parametrize("flux", [O.FLUX_LF, O.FLUX_GKS])
 def test_tangent_matches_central_differences(flux):
     """Forward-mode dual numbers through two whole steps on discontinuous data against central
@@ -868,19 +882,23 @@ def test_limited_density_wave_matches_unlimited_closely():
 
 def test_limited_map_amplifies_rounding_unlike_eq21():
     """Conditioning of the limited step (eqs. (27)-(29)) on Riemann data, which fixes how its GPU
-    parity is checked: a one-ulp perturbation of the input grows to well above rounding level in
-    ten LF steps with the limiter, and stays at rounding level with eq. (21)."""
+    parity is checked: on the 48x40 case of the GPU limiter tests, a one-ulp perturbation of the
+    input (four random sign patterns) grows to at least 1e-12 relative L1 in ten LF steps with the
+    limiter (so no implementation can be held to the 1e-12 FP64 bar over a ten-step trajectory: its
+    own rounding differs from the oracle's by that much at every step), and stays at rounding level
+    with eq. (21)."""
     pr = WL.riemann4(48, 40, seed=48)
     g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
-    Wp = pr.W * (1 + 2.2e-16 * np.random.default_rng(1).choice([-1, 1], pr.W.shape))
-    drift = {}
-    for tl in (0, 1):
-        P = O.make_params(flux=O.FLUX_LF, cfl=0.4, time_limiter=tl)
-        a = O.run(pr.W, pr.alpha, g, P, 10)[0]
-        b = O.run(Wp, pr.alpha, g, P, 10)[0]
-        drift[tl] = np.abs(a - b).sum() / np.abs(a).sum()
-    assert drift[0] <= 2e-15
-    assert drift[1] >= 1e-14
+    ref = {tl: O.run(pr.W, pr.alpha, g, O.make_params(flux=O.FLUX_LF, cfl=0.4, time_limiter=tl), 10)[0]
+           for tl in (0, 1)}
+    for seed in range(4):
+        Wp = pr.W * (1 + 2.2e-16 * np.random.default_rng(seed).choice([-1, 1], pr.W.shape))
+        drift = {}
+        for tl in (0, 1):
+            b = O.run(Wp, pr.alpha, g, O.make_params(flux=O.FLUX_LF, cfl=0.4, time_limiter=tl), 10)[0]
+            drift[tl] = max(np.abs(ref[tl][c] - b[c]).sum() / np.abs(ref[tl][c]).sum() for c in range(4))
+        assert drift[0] <= 2e-15, (seed, drift)
+        assert drift[1] >= 1e-12, (seed, drift)
 
 
 # ----------------------------------------------------------------------------------------------
