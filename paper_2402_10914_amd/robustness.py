@@ -52,32 +52,36 @@ def initial_alpha(pr, params, dtype):
     st = Stepper.for_problem(pr, params, dtype)
     W = torch.tensor(pr.W, dtype=dtype, device="cuda")
     A = torch.ones((pr.ny, pr.nx), dtype=dtype, device="cuda")
-    _, _, an = st.rhs(W, A, pr.cfl / _max_signal_speed(pr), want_alpha=True)
+    smax, _ = st.max_speed(W)
+    _, _, an = st.rhs(W, A, pr.cfl / smax, want_alpha=True)
     return an.double().cpu().numpy()
 
 
-def _max_signal_speed(pr) -> float:
-    W = pr.W
-    rho = W[0]
-    u, v = W[1] / rho, W[2] / rho
-    p = (pr.gamma - 1.0) * (W[3] - 0.5 * rho * (u * u + v * v))
-    c = np.sqrt(pr.gamma * p / rho)
-    return float(max(((np.abs(u) + c) / pr.dx).max(), ((np.abs(v) + c) / pr.dy).max()))
+def max_signal_speed(pr, dtype=None) -> float:
+    """The CFL reduction of the initial state on the GPU (the library's dfw_max_speed)."""
+    import torch
+    from .api import Params, Stepper
+    dtype = torch.float64 if dtype is None else dtype
+    st = Stepper.for_problem(pr, Params(gamma=pr.gamma), dtype)
+    smax, _ = st.max_speed(torch.tensor(pr.W, dtype=dtype, device="cuda"))
+    return smax
 
 
-def step_cap(pr) -> int:
-    """Upper bound on the steps to the problem's end: four times the steps the initial signal
-    speed would need (the speeds of these flows grow by well under that factor)."""
+def step_cap(pr, smax: float) -> int:
+    """Upper bound on the steps to the problem's end, given the initial state's maximum signal speed
+    over the cell size (the CFL reduction): four times the steps that speed would need (the speeds
+    of these flows grow by well under that factor)."""
     t_end = pr.extra.get("t_end", 0.0)
     if t_end <= 0.0:
         return pr.nsteps
-    dt0 = pr.cfl / _max_signal_speed(pr)
+    dt0 = pr.cfl / smax
     return int(math.ceil(4.0 * t_end / dt0)) + 20
 
 
-def survives(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None, alpha0: str = "one",
-             ablation: dict | None = None):
-    """Runs the problem at every Mach number of `machs` as one batch; returns [bool] (survived)."""
+def run_batch(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None, alpha0: str = "one",
+              ablation: dict | None = None):
+    """Runs the problem at every Mach number of `machs` as one batch (one captured hipGraph) to its
+    end; returns (final time per run, failing step per run or -1, step cap)."""
     import torch
     from .api import Batch
     dtype = torch.float64 if dtype is None else dtype
@@ -92,8 +96,16 @@ def survives(problem: str, machs, solver: str, recon: str, n: int | None = None,
         raise ValueError(f"unknown alpha0 {alpha0!r}")
     b = Batch([(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y) for p in probs], params, dtype, 0)
     W, A = b.pack([p.W for p in probs], [p.alpha for p in probs])
-    nsteps = max(step_cap(p) for p in probs)
+    nsteps = max(step_cap(p, max_signal_speed(p, dtype)) for p in probs)
     t, fs = b.run(W, A, nsteps, use_graph=True)
+    return t, fs, nsteps
+
+
+def survives(problem: str, machs, solver: str, recon: str, n: int | None = None, dtype=None, alpha0: str = "one",
+             ablation: dict | None = None):
+    """Runs the problem at every Mach number of `machs` as one batch; returns [bool] (survived)."""
+    t, fs, nsteps = run_batch(problem, machs, solver, recon, n, dtype, alpha0, ablation)
+    t_end = WL.ROBUSTNESS[problem](float(machs[0]), **({} if n is None else {"n": n})).extra.get("t_end", 0.0)
     out = []
     for ti, f in zip(t, fs):
         if f != -1:

@@ -6,6 +6,8 @@ import math
 import numpy as np
 import pytest
 
+import oracle as O
+
 from paper_2402_10914_amd import robustness as R
 from paper_2402_10914_amd import workloads as WL
 
@@ -85,10 +87,57 @@ def test_bisection_open_ends():
     assert r["max_mach"] == 50.0 and r["first_fail"] is None
 
 
+def _oracle_smax(pr):
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    return O.max_speed(pr.W, g, O.make_params(gamma=pr.gamma))[0]
+
+
 def test_step_cap_covers_the_run():
     pr = WL.problem_123(10.0)
     dt0 = 0.5 * pr.dx / (2.0 + 2.0 / 10.0)
-    assert R.step_cap(pr) >= 4 * 0.14 / dt0
-    assert R.step_cap(WL.hurricane(3.0, n=40)) == 50
+    assert R.step_cap(pr, _oracle_smax(pr)) >= 4 * 0.14 / dt0
+    hur = WL.hurricane(3.0, n=40)
+    assert R.step_cap(hur, _oracle_smax(hur)) == 50
     with pytest.raises(ValueError):
         R.solver_params("roe", "hybrid")
+
+
+def _switch_counts(problem, mach, solver, n=None, steps=30):
+    """Oracle run with the hybrid switch as printed (eq. (42)), one step at a time: per completed
+    step the number of cells whose own DF is below the threshold and the number of (cell, direction)
+    pairs meeting the printed condition (the DF of the cell and both neighbours along the direction
+    below the threshold); stops at the failing step."""
+    pr = WL.ROBUSTNESS[problem](mach) if n is None else WL.ROBUSTNESS[problem](mach, n=n)
+    p = R.solver_params(solver, "hybrid", pr.extra.get("t_end", 0.0))
+    P = O.make_params(flux=p.flux, cfl=p.cfl, alpha_thres=p.alpha_thres, switch_rule=p.switch_rule,
+                      time_limiter=p.time_limiter, time_scheme=p.time_scheme, t_end=p.t_end)
+    g = O.make_grid(pr.nx, pr.ny, pr.dx, pr.dy, pr.bc_x, pr.bc_y)
+    W, a = pr.W, pr.alpha
+    out = []
+    for _ in range(steps):
+        W, a, _, _, fs = O.run(W, a, g, P, 1)
+        if fs != -1:
+            return out, True
+        pad = np.pad(a, 1, mode="edge")  # transmissive boundaries
+        trip = 0
+        for ax in ((0, 1), (1, 0)):
+            if a.shape[1 if ax[1] else 0] == 1:
+                continue
+            nb = [pad[1 + dj:1 + dj + a.shape[0], 1 + di:1 + di + a.shape[1]] for dj, di in ((-ax[0], -ax[1]), (0, 0), (ax[0], ax[1]))]
+            trip += int((np.maximum(np.maximum(nb[0], nb[1]), nb[2]) < 0.5).sum())
+        out.append((int((a < 0.5).sum()), trip))
+    return out, False
+
+
+def test_printed_switch_stays_off_at_isolated_jumps():
+    """Finding behind reading R31 (Section 4.3, Table 5): on the 123 problem the DF drops below the
+    threshold in the two cells beside the central jump only, so the printed condition (three
+    consecutive cells below 0.5) never holds and the hybrid run equals WENO-AO up to its failure;
+    on the planar rarefactions the low-DF zone is wider than two cells and the condition holds."""
+    for solver in ("gks", "lf"):
+        counts, failed = _switch_counts("123", 3.0, solver)
+        assert failed and counts
+        assert counts[0][0] == 2
+        assert all(trip == 0 for _, trip in counts)
+    counts, failed = _switch_counts("rarefaction", 3.0, "lf", n=100)
+    assert counts and counts[0][1] > 0
