@@ -1,12 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the S2O4 DF-hybrid step (Zhang, Ji & Xu, arXiv:2402.10914) on one MI355X.
 
-Default workload: 2-D Euler, FP64, 512 x 512 cells on [0,1]^2, transmissive boundaries, seeded
-four-quadrant Riemann data (seed 2402), gas-kinetic flux, WENO-AO + DF, S2O4, CFL 0.4; one "step"
-is one S2O4 time step of the whole grid (all parts of the path: CFL reduction, ghost fill, DF,
-reconstruction, fluxes with time derivatives, two-stage update).  The timed region runs exactly
---steps steps from the initial condition after --warmup untimed steps; inputs are resident in HBM
-before timing starts.
+Default workload: 2-D Euler, FP64, 4096 x 4096 cells on periodic [0,2]^2: a density-wave background
+with 32 seeded circular regions (seed 10914; density ratios up to 10, pressure ratios up to 1e3; each
+region's edge smoothed over two cells by a tanh profile, since the scheme has no positivity limiter
+and fails in the first step on point-sampled sharp edges), gas-kinetic flux, WENO-AO + DF, S2O4,
+CFL 0.4, the first 50 steps of the run.  One "step" is one S2O4 time step of the whole grid (all
+parts of the path: CFL reduction, ghost fill, DF, reconstruction, fluxes with time derivatives,
+two-stage update).  The timed region runs exactly --steps steps from the initial condition after
+--warmup untimed steps; inputs are resident in HBM before timing starts.  The interface tile shape
+is the autotuner's pick for this grid (--tile overrides it).  --workload circles4096_lf (LF flux),
+circles4096_gks_f32 / circles4096_lf_f32 (FP32) and riemann512_gks / riemann512_lf (512 x 512
+four-quadrant Riemann data, transmissive) select the other configurations.
 
 Prints one JSON line: cell-updates/s, per-kernel roofline of the dominant kernel (FP64 vector ALU
 bound: its algorithmic flops per launch over its mean launch time, measured with HIP events on the
@@ -74,24 +79,41 @@ def workload(name):
         return WL.riemann4(512, seed=2402, flux=WL.FLUX_GKS, cfl=0.4, nsteps=200), "f64"
     if name == "riemann512_lf":
         return WL.riemann4(512, seed=2402, flux=WL.FLUX_LF, cfl=0.4, nsteps=200), "f64"
-    if name.startswith("circles4096"):
+    if name in ("circles4096_gks", "circles4096_lf", "circles4096_gks_f32", "circles4096_lf_f32"):
         flux = WL.FLUX_GKS if "gks" in name else WL.FLUX_LF
         return WL.circles(4096, seed=10914, flux=flux, cfl=0.4, nsteps=50), ("f32" if name.endswith("f32") else "f64")
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(prob, steps, time_limiter=0, time_scheme=0):
-    """The oracle as it stands on this host: `steps` steps of the same grid."""
+def workload_text(prob, tl, ts):
+    flux = "GKS" if prob.flux else "LF"
+    scheme = f"{'SSP-RK3' if ts else 'S2O4'}{', time limiter' if tl else ''}"
+    if prob.name == "riemann4":
+        return f"{prob.nx}x{prob.ny} four-quadrant Riemann, {flux}, WENO-AO+DF, {scheme}, CFL 0.4, transmissive"
+    return (f"{prob.nx}x{prob.ny} periodic density wave + 32 circles (rho ratio <= 10, p ratio <= 1e3, "
+            f"edges tanh-smoothed over 2 cells), {flux}, WENO-AO+DF, {scheme}, CFL 0.4, first 50 steps")
+
+
+def cpu_baseline(prob, steps, cells, time_limiter=0, time_scheme=0):
+    """The oracle as it stands on this host: `steps` steps of the central cells x cells part of the
+    workload's initial state (the whole grid when it is smaller), same boundary types."""
+    import numpy as np
+
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    g = O.make_grid(prob.nx, prob.ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y)
+    nx, ny = min(cells, prob.nx), min(cells, prob.ny)
+    i0, j0 = (prob.nx - nx) // 2, (prob.ny - ny) // 2
+    W = np.ascontiguousarray(prob.W[:, j0:j0 + ny, i0:i0 + nx])
+    A = np.ascontiguousarray(prob.alpha[j0:j0 + ny, i0:i0 + nx])
+    g = O.make_grid(nx, ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y)
     p = O.make_params(flux=prob.flux, cfl=prob.cfl, time_limiter=time_limiter, time_scheme=time_scheme)
     t0 = time.perf_counter()
-    O.run(prob.W, prob.alpha, g, p, steps)
+    O.run(W, A, g, p, steps)
     el = time.perf_counter() - t0
-    return {"value": prob.nx * prob.ny * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} {'SSP-RK3' if time_scheme else 'S2O4'} steps of the same {prob.nx}x{prob.ny} grid from the same initial state "
-                      f"({el:.1f} s, OpenMP over rows)"}
+    part = "the whole grid" if (nx, ny) == (prob.nx, prob.ny) else f"the central {nx}x{ny} cells of the {prob.nx}x{prob.ny} grid"
+    return {"value": nx * ny * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} {'SSP-RK3' if time_scheme else 'S2O4'} step(s) of {part} from the same initial state, "
+                      f"same flux and boundary types ({el:.1f} s, OpenMP over rows)"}
 
 
 def batch_compare(nsteps=100, tune=True):
@@ -207,10 +229,13 @@ def copy_mode(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="riemann512_gks")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="circles4096_gks")
+    ap.add_argument("--tile", type=int, default=-1, help="interface tile shape (default: the autotuner's pick)")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-cells", type=int, default=2048,
+                    help="the CPU baseline runs the oracle on the central cpu-cells x cpu-cells part of the grid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -242,6 +267,11 @@ def main():
         raise SystemExit("--ssprk3 runs with the LF flux and without the time limiter")
     params = api.Params(flux=prob.flux, cfl=prob.cfl, time_limiter=tl, time_scheme=ts)
     default_form = not (tl or ts)
+    if args.tile >= 0:
+        params.tile = args.tile
+    else:
+        from paper_2402_10914_amd import autotune
+        params.tile, _ = autotune.tune_grid(prob, params, dtype)
     st = api.Stepper.for_problem(prob, params, dtype)
     W0 = torch.tensor(prob.W, dtype=dtype, device="cuda")
     A0 = torch.tensor(prob.alpha, dtype=dtype, device="cuda")
@@ -259,10 +289,12 @@ def main():
     t_sim, fail = st.run(W, A, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # a run that meets a non-physical state skips its later steps: count the steps that ran
+    done = args.steps if fail == -1 else fail
     if fail != -1:
-        print(f"# non-physical state after {fail} steps", file=sys.stderr)
+        print(f"# non-physical state after {fail} steps: only those are counted", file=sys.stderr)
     cells = prob.nx * prob.ny
-    value = cells * args.steps / elapsed
+    value = cells * done / elapsed
     print(f"# timed {args.steps} steps in {elapsed * 1e3:.2f} ms -> {value:.4e} cell-updates/s (t_sim {t_sim:.5f})",
           file=sys.stderr, flush=True)
 
@@ -309,21 +341,23 @@ def main():
         "vs_baseline": None,
         "dtype": dt_name,
         "data": "synthetic",
-        "config": {"workload": (f"{prob.nx}x{prob.ny} four-quadrant Riemann, {'GKS' if prob.flux else 'LF'}, WENO-AO+DF, "
-                                f"{'SSP-RK3' if ts else 'S2O4'}{', time limiter' if tl else ''}, CFL 0.4, transmissive")
-                               if prob.name == "riemann4" else f"{prob.nx}x{prob.ny} {prob.name}",
+        "config": {"workload": workload_text(prob, tl, ts),
                    "name": args.workload, "nx": prob.nx, "ny": prob.ny, "flux": "gks" if prob.flux else "lf",
-                   "time_scheme": "ssprk3" if ts else "s2o4", "time_limiter": bool(tl), "parallelism": "single GPU"},
+                   "time_scheme": "ssprk3" if ts else "s2o4", "time_limiter": bool(tl), "tile": params.tile,
+                   "parallelism": "single GPU"},
+        "fail_step": fail,
         "roofline": roofline,
         "hbm_algorithmic": {"bytes_per_cell_update": BYTES_PER_CELL_UPDATE[esize], "achieved_GBps": round(hbm, 1),
                             "peak_GBps": PEAK_HBM, "frac": round(hbm / PEAK_HBM, 4)} if default_form else None,
         "flops_per_cell_update": flops.per_cell_update(prob.flux) if default_form else None,
         "kernels": kernels,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps, tl, ts),
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps, args.cpu_cells, tl, ts),
         "batched": None if args.no_batch else batch_compare(),
         "adjoint": None if args.no_adjoint else adjoint_compare(),
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    if fail != -1:
+        sys.exit(3)
 
 
 if __name__ == "__main__":

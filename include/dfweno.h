@@ -114,8 +114,12 @@ dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params*
                    int32_t dtype, void* ws, size_t ws_bytes, double* dt_hist_dev, double* t_out,
                    int32_t* fail_step, void* stream);
 
-/* The CFL reduction alone: smax = max over cells of max((|U|+c)/dx, (|V|+c)/dy).
- *   W device in; smax (host, FP64) and nonphys (host, 0/1) out.  Synchronises `stream`. */
+/* The CFL reduction alone (Algorithm 1, the step that sets the time increment from the CFL
+ * condition; the paper gives no formula, so dt = cfl / smax with
+ * smax = max over cells of max((|U|+c)/dx, (|V|+c)/dy), c = sqrt(gamma p / rho)).
+ *   W device in, [4][ny][nx]; smax (host, FP64) out; nonphys (host) out: 1 if any cell has
+ *   rho <= 0, p <= 0 or a non-finite value (those cells do not enter smax), else 0.
+ *   ws: the dfw_run workspace (its control block is used).  Synchronises `stream`. */
 dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* params, int32_t dtype,
                          void* ws, size_t ws_bytes, double* smax, int32_t* nonphys, void* stream);
 

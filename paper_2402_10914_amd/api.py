@@ -78,6 +78,32 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _same_device(t: torch.Tensor, device: torch.device) -> bool:
+    if t.device.type != "cuda":
+        return False
+    want = device.index if device.index is not None else torch.cuda.current_device()
+    return t.device.index == want
+
+
+def _require(t: torch.Tensor, name: str, dtype: torch.dtype, device: torch.device, numel: int | None = None,
+             shape: tuple | None = None, at_least: bool = False):
+    """Raises ValueError unless t is a contiguous tensor of `dtype` on the CUDA device `device` with the
+    given shape or element count (at least `numel` elements when at_least), so that no host pointer
+    and no strided view ever reaches a kernel."""
+    ok = isinstance(t, torch.Tensor) and t.dtype == dtype and t.is_contiguous() and _same_device(t, device)
+    if ok and shape is not None:
+        ok = tuple(t.shape) == tuple(shape)
+    if ok and numel is not None:
+        ok = t.numel() >= numel if at_least else t.numel() == numel
+    if not ok:
+        msg = f"{name} must be a contiguous {dtype} tensor on {device}"
+        if shape is not None:
+            msg += f" of shape {tuple(shape)}"
+        if numel is not None:
+            msg += f" with {'at least ' if at_least else ''}{numel} elements"
+        raise ValueError(msg)
+
+
 class Stepper:
     """Owns the device workspace for one grid and element type."""
 
@@ -104,11 +130,9 @@ class Stepper:
 
     def _check(self, W: torch.Tensor, alpha: torch.Tensor | None = None):
         g = self.grid
-        if W.shape != (4, g.ny, g.nx) or W.dtype != self.dtype or not W.is_contiguous() or W.device.type != "cuda":
-            raise ValueError(f"W must be a contiguous {self.dtype} CUDA tensor of shape (4, {g.ny}, {g.nx})")
-        if alpha is not None and (alpha.shape != (g.ny, g.nx) or alpha.dtype != self.dtype
-                                  or not alpha.is_contiguous() or alpha.device.type != "cuda"):
-            raise ValueError(f"alpha must be a contiguous {self.dtype} CUDA tensor of shape ({g.ny}, {g.nx})")
+        _require(W, "W", self.dtype, self.device, shape=(4, g.ny, g.nx))
+        if alpha is not None:
+            _require(alpha, "alpha", self.dtype, self.device, shape=(g.ny, g.nx))
 
     def run(self, W: torch.Tensor, alpha: torch.Tensor, nsteps: int, dt_hist: torch.Tensor | None = None,
             params: Params | None = None, strict: bool = False):
@@ -116,9 +140,8 @@ class Stepper:
         is TIME_SSPRK3).  Returns (t, fail_step); fail_step is -1
         unless a non-physical state was met (then W holds it; strict=True raises instead)."""
         self._check(W, alpha)
-        if dt_hist is not None and (dt_hist.dtype != torch.float64 or dt_hist.numel() < nsteps
-                                    or not dt_hist.is_contiguous()):
-            raise ValueError("dt_hist must be a contiguous float64 CUDA tensor with >= nsteps entries")
+        if dt_hist is not None:
+            _require(dt_hist, "dt_hist", torch.float64, self.device, numel=nsteps, at_least=True)
         p = (params or self.params).struct()
         t = ctypes.c_double(0.0)
         fs = ctypes.c_int32(-1)
@@ -209,10 +232,10 @@ class Batch:
     def run(self, Wf: torch.Tensor, Af: torch.Tensor, nsteps: int, use_graph: bool = True,
             dt_hist: torch.Tensor | None = None):
         """Advance every grid in place.  Returns (t per grid, fail step per grid)."""
-        if Wf.numel() != self.w_elems or Af.numel() != self.a_elems or Wf.dtype != self.dtype or Af.dtype != self.dtype:
-            raise ValueError("packed arrays do not match the plan")
-        if dt_hist is not None and (dt_hist.dtype != torch.float64 or dt_hist.numel() < self.ngrids * nsteps):
-            raise ValueError("dt_hist must be float64 with ngrids * nsteps entries")
+        _require(Wf, "packed W", self.dtype, self.device, numel=self.w_elems)
+        _require(Af, "packed alpha", self.dtype, self.device, numel=self.a_elems)
+        if dt_hist is not None:
+            _require(dt_hist, "dt_hist", torch.float64, self.device, numel=self.ngrids * nsteps, at_least=True)
         t = (ctypes.c_double * self.ngrids)()
         fs = (ctypes.c_int32 * self.ngrids)()
         st = self.lib.dfw_batch_run(self.handle, _ptr(Wf), _ptr(Af), int(nsteps), self.ws_ptr, self.ws_bytes,

@@ -1053,14 +1053,21 @@ static dfw_status check_ws(const dfw_grid* g, int32_t dtype, void* ws, size_t ws
   return DFW_OK;
 }
 
-dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
-                   int32_t dtype, void* ws, size_t ws_bytes, double* dt_hist_dev, double* t_out,
-                   int32_t* fail_step, void* stream) {
+static dfw_status check_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
+                            int32_t dtype) {
   dfw_status s = check_common(grid, params, dtype);
   if (s != DFW_OK) return s;
   if (!W || !alpha) return fail(DFW_EINVAL, "W and alpha must be non-null");
   if (nsteps < 0) return fail(DFW_EINVAL, "nsteps must be >= 0");
   if (!(params->dt_fixed > 0) && !(params->cfl > 0)) return fail(DFW_EINVAL, "need cfl > 0 or dt_fixed > 0");
+  return DFW_OK;
+}
+
+dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
+                   int32_t dtype, void* ws, size_t ws_bytes, double* dt_hist_dev, double* t_out,
+                   int32_t* fail_step, void* stream) {
+  dfw_status s = check_run(W, alpha, grid, params, nsteps, dtype);
+  if (s != DFW_OK) return s;
   if ((s = check_ws(grid, dtype, ws, ws_bytes)) != DFW_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if (dtype == DFW_F64)
@@ -1180,11 +1187,22 @@ dfw_status dfw_batch_plan(const dfw_grid* grids, int32_t ngrids, const dfw_param
     const size_t ncb = (N + kCellBlock - 1) / kCellBlock;
     for (size_t k = 0; k < ncb; ++k) b->cblocks.push_back(make_int2(g, (int)(k * kCellBlock)));
   }
-  if (b->w_elems >= ((size_t)1 << 40) || b->tiles.size() > ((size_t)1 << 30)) {
+  if (b->w_elems >= ((size_t)1 << 40)) {
     delete b;
-    return fail(DFW_EINVAL, "batch too large");
+    return fail(DFW_EINVAL, "batch too large (more than 2^38 cells)");
   }
   build_tiles(b, order);
+  // one launch covers every tile (cell block) of the batch: the work items of a launch must stay below
+  // 2^32, and the block counts are passed to the launch as int
+  const size_t max_items = 0xffffffffull;
+  const size_t tile_threads = (size_t)kShapes[b->params.tile].tf * (kShapes[b->params.tile].tr + 4);
+  if (b->tiles.size() > (size_t)INT32_MAX || b->cblocks.size() > (size_t)INT32_MAX ||
+      b->tiles.size() * tile_threads > max_items || b->cblocks.size() * kCellBlock > max_items) {
+    const size_t nt = b->tiles.size(), nc = b->cblocks.size();
+    delete b;
+    return fail(DFW_EINVAL, "batch too large for one launch: " + std::to_string(nt) + " interface tiles, " +
+                                std::to_string(nc) + " cell blocks");
+  }
   size_t off = 0;
   b->ws_off = off;
   off = align256(off + b->w_elems * es);

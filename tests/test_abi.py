@@ -137,3 +137,41 @@ def test_adjoint_validation_without_gpu():
     assert call(_params(), ckpt_bytes=ck - 1) == _lib.DFW_EINVAL
     assert L.dfw_run_ckpt(4096, 8192, ctypes.byref(g), ctypes.byref(_params()), n, 0, 0, 1 << 20, ck, 1 << 24,
                           1 << 30, 4096, None, None, None) == _lib.DFW_EINVAL  # ckpt_every = 0
+
+
+def _host_stepper(nx=8, ny=6):
+    """A Stepper whose arguments are checked without a GPU (no workspace, no library calls)."""
+    import torch
+    from paper_2402_10914_amd import _lib, api
+    st = api.Stepper.__new__(api.Stepper)
+    st.grid = _lib.dfw_grid(nx, ny, 0.1, 0.1, 0, 0)
+    st.params = api.Params()
+    st.dtype = torch.float64
+    st.device = torch.device("cuda", 0)
+    st.lib = None  # any library call would fail: the checks must raise first
+    return st
+
+
+def test_host_tensors_are_rejected_before_any_launch():
+    """Host tensors, strided views and mismatched dt_hist raise ValueError in the binding, so no
+    host pointer or strided view reaches a kernel."""
+    import torch
+    from paper_2402_10914_amd import api
+    st = _host_stepper()
+    W = torch.zeros(4, 6, 8, dtype=torch.float64)
+    A = torch.ones(6, 8, dtype=torch.float64)
+    with pytest.raises(ValueError, match="W must be"):
+        st.run(W, A, 1)
+    with pytest.raises(ValueError, match="W must be"):
+        st.run(torch.zeros(4, 8, 6, dtype=torch.float64).transpose(1, 2), A, 1)
+    with pytest.raises(ValueError, match="W must be"):
+        st.max_speed(W)
+    with pytest.raises(ValueError):
+        st.rhs(W, A, 1e-3)
+    b = api.Batch.__new__(api.Batch)
+    b.ngrids, b.w_elems, b.a_elems = 2, 40, 10
+    b.dtype, b.device, b.lib, b.handle = torch.float64, torch.device("cuda", 0), None, None
+    with pytest.raises(ValueError, match="packed W"):
+        b.run(torch.zeros(40, dtype=torch.float64), torch.zeros(10, dtype=torch.float64), 1)
+    with pytest.raises(ValueError, match="packed W"):
+        b.run(torch.zeros(80, dtype=torch.float64)[::2], torch.zeros(10, dtype=torch.float64), 1)
