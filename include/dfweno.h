@@ -114,6 +114,24 @@ dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params*
                    int32_t dtype, void* ws, size_t ws_bytes, double* dt_hist_dev, double* t_out,
                    int32_t* fail_step, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): dfw_run with its workspace in a fixed device array of
+ * DFW_NOALLOC_SCRATCH_BYTES bytes inside the library instead of a caller-provided one.  Same
+ * arguments, results and synchronisation as dfw_run, minus ws / ws_bytes.  Calls no hipMalloc,
+ * hipFree or other allocating routine.
+ *   Limit: dfw_workspace_bytes(grid, dtype) must not exceed DFW_NOALLOC_SCRATCH_BYTES (64 MiB: up to
+ *   about 299 000 cells in FP64, e.g. 512 x 512; about 599 000 in FP32); larger grids return
+ *   DFW_EWORKSPACE before anything is launched.
+ *   The array is per GPU (the current device; `stream` must belong to it), allocated when the
+ *   library is loaded and held until the process ends; its address is looked up once per device at
+ *   the first call there.  Every call on a GPU shares that GPU's array and leaves its contents
+ *   behind; each call initialises the part that must start at zero (the control block) with a
+ *   kernel of its own.  Calls that overlap on one GPU (other streams or threads) race on the array
+ *   and must be serialised by the caller. */
+#define DFW_NOALLOC_SCRATCH_BYTES (64u << 20)
+dfw_status dfw_run_noalloc(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
+                           int32_t dtype, double* dt_hist_dev, double* t_out, int32_t* fail_step, void* stream);
+
 /* The CFL reduction alone (Algorithm 1, the step that sets the time increment from the CFL
  * condition; the paper gives no formula, so dt = cfl / smax with
  * smax = max over cells of max((|U|+c)/dx, (|V|+c)/dy), c = sqrt(gamma p / rho)).

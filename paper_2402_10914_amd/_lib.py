@@ -20,6 +20,7 @@ DFW_F64, DFW_F32 = 0, 1
 KERNEL_KINDS = ["faces1", "update1", "faces2", "update2", "speed", "graph", "adj_faces1", "adj_faces2",
                 "adj_gather", "rk_faces", "rk_update"]
 DFW_ORDER_GRID, DFW_ORDER_LARGEST_FIRST, DFW_ORDER_INTERLEAVED = 0, 1, 2
+DFW_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class dfw_grid(ctypes.Structure):
@@ -55,6 +56,7 @@ SIGNATURES = {
     "dfw_workspace_bytes": (ctypes.c_size_t, [_GP, ctypes.c_int32]),
     "dfw_run": (ctypes.c_int32, [_VP, _VP, _GP, _PP, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t,
                                  _VP, _DP, _IP, _VP]),
+    "dfw_run_noalloc": (ctypes.c_int32, [_VP, _VP, _GP, _PP, ctypes.c_int32, ctypes.c_int32, _VP, _DP, _IP, _VP]),
     "dfw_max_speed": (ctypes.c_int32, [_VP, _GP, _PP, ctypes.c_int32, _VP, ctypes.c_size_t, _DP, _IP, _VP]),
     "dfw_rhs": (ctypes.c_int32, [_VP, _VP, _GP, _PP, ctypes.c_int32, ctypes.c_double, _VP, _VP, _VP, _VP,
                                  ctypes.c_size_t, _VP]),

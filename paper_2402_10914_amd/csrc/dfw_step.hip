@@ -22,6 +22,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1075,6 +1076,55 @@ dfw_status dfw_run(void* W, void* alpha, const dfw_grid* grid, const dfw_params*
                             fail_step, st);
   return run_impl<float>((float*)W, (float*)alpha, grid, params, nsteps, (char*)ws, dt_hist_dev, t_out, fail_step,
                          st);
+}
+
+}  // extern "C"
+
+// ---- workspace in a fixed device array (dfw_run_noalloc) ----
+// Each GPU the library runs on holds its own copy of `scratch` until the process ends.  On the host
+// the name stands for a host-side shadow, not a device address: kernels and copies take the
+// address hipGetSymbolAddress returns for the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[DFW_NOALLOC_SCRATCH_BYTES];
+
+namespace dfw {
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static dfw_status scratch_for_current_device(char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DFW_EHIP, "device index " + std::to_string(dev) + " out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DFW_EHIP, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return DFW_OK;
+}
+}  // namespace dfw
+
+extern "C" {
+
+dfw_status dfw_run_noalloc(void* W, void* alpha, const dfw_grid* grid, const dfw_params* params, int32_t nsteps,
+                           int32_t dtype, double* dt_hist_dev, double* t_out, int32_t* fail_step, void* stream) {
+  dfw_status s = check_run(W, alpha, grid, params, nsteps, dtype);
+  if (s != DFW_OK) return s;
+  const size_t need = layout(grid, dtype == DFW_F32 ? 4 : 8).total;
+  if (need > (size_t)DFW_NOALLOC_SCRATCH_BYTES)
+    return fail(DFW_EWORKSPACE, "grid " + std::to_string(grid->nx) + "x" + std::to_string(grid->ny) + " needs " +
+                                    std::to_string(need) + " bytes of workspace; the fixed scratch array holds " +
+                                    std::to_string((size_t)DFW_NOALLOC_SCRATCH_BYTES) + " (use dfw_run)");
+  char* ws = nullptr;
+  if ((s = scratch_for_current_device(&ws)) != DFW_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == DFW_F64)
+    return run_impl<double>((double*)W, (double*)alpha, grid, params, nsteps, ws, dt_hist_dev, t_out, fail_step, st);
+  return run_impl<float>((float*)W, (float*)alpha, grid, params, nsteps, ws, dt_hist_dev, t_out, fail_step, st);
 }
 
 dfw_status dfw_max_speed(const void* W, const dfw_grid* grid, const dfw_params* params, int32_t dtype, void* ws,
