@@ -73,7 +73,11 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   const real dt = real(dt_hist[step]);
   const Coef<real> k = make_coef<real, RULE>(S);
 
-  // ---- stage cells (rows t0-4 .. t0+TR+3) and alpha in LDS, local component order
+  // ---- stage cells (rows t0-4 .. t0+TR+3) and alpha in LDS, local component order; tiles whose halo
+  //      lies inside the grid skip the boundary index map (uniform over the workgroup)
+  const bool inner = f0 - 3 >= 0 && f0 + T::WN - 3 <= Nn && t0 - 4 >= 0 && t0 + T::NQ - 4 <= Nt;
+  auto map_n = [&](int i) { return inner ? i : bc_map(i, Nn, bcn); };
+  auto map_t = [&](int i) { return inner ? i : bc_map(i, Nt, bct); };
   for (int e = tid; e < T::NQ * T::WN; e += T::NT) {
     int nl, tl;
     if (dir == 0) {
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
       nl = e / T::NQ;
       tl = e % T::NQ;
     }
-    const int n = bc_map(f0 - 3 + nl, Nn, bcn), t = bc_map(t0 - 4 + tl, Nt, bct);
+    const int n = map_n(f0 - 3 + nl), t = map_t(t0 - 4 + tl);
     const size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
     sW[0][tl][nl] = W[g];
     sW[1][tl][nl] = W[(dir ? 2 : 1) * N + g];
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
       nl = e / T::NQ;
       tl = e % T::NQ;
     }
-    const int n = bc_map(f0 - 2 + nl, Nn, bcn), t = bc_map(t0 - 4 + tl, Nt, bct);
+    const int n = map_n(f0 - 2 + nl), t = map_t(t0 - 4 + tl);
     sA[tl][nl] = alpha[dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t];
   }
   __syncthreads();

@@ -206,7 +206,12 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   const Coef<real> k = make_coef<real>(S);
 
   // ---- stage cells and alpha into LDS (ghost cells by index mapping); component order local:
-  //      0 rho, 1 normal momentum, 2 tangential momentum, 3 energy
+  //      0 rho, 1 normal momentum, 2 tangential momentum, 3 energy.  Tiles whose halo lies inside the
+  //      grid (all but the tiles at the boundaries) skip the index map, whose periodic branch is an
+  //      integer remainder per index; the test is uniform over the workgroup.
+  const bool inner = f0 - 3 >= 0 && f0 + T::WN - 3 <= Nn && t0 - 2 >= 0 && t0 + T::NR - 2 <= Nt;
+  auto map_n = [&](int i) { return inner ? i : bc_map(i, Nn, bcn); };
+  auto map_t = [&](int i) { return inner ? i : bc_map(i, Nt, bct); };
   for (int e = tid; e < T::NR * T::WN; e += T::NT) {
     int nl, tl;
     if (dir == 0) {
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
       nl = e / T::NR;
       tl = e % T::NR;
     }
-    int n = bc_map(f0 - 3 + nl, Nn, bcn), t = bc_map(t0 - 2 + tl, Nt, bct);
+    int n = map_n(f0 - 3 + nl), t = map_t(t0 - 2 + tl);
     size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
     sW[0][tl][nl] = W[g];
     sW[1][tl][nl] = W[(dir ? 2 : 1) * N + g];
@@ -232,7 +237,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
       nl = e / T::NR;
       tl = e % T::NR;
     }
-    int n = bc_map(f0 - 2 + nl, Nn, bcn), t = bc_map(t0 - 2 + tl, Nt, bct);
+    int n = map_n(f0 - 2 + nl), t = map_t(t0 - 2 + tl);
     size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
     sA[tl][nl] = alpha[g];
   }
