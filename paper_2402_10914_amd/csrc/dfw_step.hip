@@ -108,6 +108,16 @@ __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
   return k;
 }
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup b to XCD b mod 8), and each XCD has
+// its own L2.  Tile order for launches over interface tiles: the workgroups of one XCD take one
+// contiguous run of the tile list, so neighbouring tiles, which stage overlapping halos, share an L2.
+// A bijection of [0, n).
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ int bc_map(int i, int n, int bc) {
   if (bc == DFW_BC_PERIODIC) {
     int r = i % n;
@@ -159,7 +169,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
     G = grids[gi];
   } else {
     G = G0;
-    int b = blockIdx.x;
+    int b = xcd_tile(blockIdx.x, gridDim.x);
     const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
     dir = b < nbx ? 0 : 1;
     if (dir) b -= nbx;
@@ -1014,15 +1024,20 @@ static void build_tiles(dfw_batch* b, int order) {
         }
     }
   }
+  std::vector<int4> list;
   if (order == DFW_ORDER_INTERLEAVED) {  // round-robin over grids: neighbouring workgroups differ in grid
     size_t longest = 0;
     for (int g : idx) longest = std::max(longest, per_grid[g].size());
     for (size_t k = 0; k < longest; ++k)
       for (int g : idx)
-        if (k < per_grid[g].size()) b->tiles.push_back(per_grid[g][k]);
+        if (k < per_grid[g].size()) list.push_back(per_grid[g][k]);
   } else {
-    for (int g : idx) b->tiles.insert(b->tiles.end(), per_grid[g].begin(), per_grid[g].end());
+    for (int g : idx) list.insert(list.end(), per_grid[g].begin(), per_grid[g].end());
   }
+  // workgroup b runs list entry xcd_tile(b): each XCD takes a contiguous run of the order above
+  const int n = (int)list.size();
+  b->tiles.resize(list.size());
+  for (int w = 0; w < n; ++w) b->tiles[w] = list[xcd_tile(w, n)];
 }
 
 template <class real>
