@@ -491,7 +491,7 @@ struct AdjShape {
   int tf, tr;
 };
 // Interface tiles of the adjoint kernel, per flux (LF, GKS).
-static constexpr AdjShape kAdjShapes[2] = {{8, 28}, {8, 12}};
+static constexpr AdjShape kAdjShapes[2] = {{4, 60}, {8, 12}};
 
 static int adj_tiles(int flux, int nx, int ny) {
   const AdjShape s = kAdjShapes[flux];
