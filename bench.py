@@ -17,8 +17,9 @@ Prints one JSON line: cell-updates/s, per-kernel roofline of the dominant kernel
 bound: its algorithmic flops per launch over its mean launch time, measured with HIP events on the
 launch stream) and the CPU oracle timed on a bounded sample on this host.
 
-Also reported: the batched form against the per-grid loop ("batched") and the cost of the
-gradient of a 100-step rollout against the rollout itself ("adjoint").
+Also reported: the batched form against the per-grid loop ("batched"), the cost of the gradient of
+a 100-step rollout against the rollout itself ("adjoint"), and the circles workload as configured,
+with sharp point-sampled edges, on the LF flux, which runs it ("sharp_edges_lf").
 
 Other modes:  --mode copy      plain device copy of known size (calibrates rocprofv3 FETCH/WRITE_SIZE).
               --mode adjoint   the gradient measurement alone.
@@ -211,6 +212,33 @@ def adjoint_compare(n=1024, nsteps=100, every=10):
             "checkpoint_bytes": adj.ckpt_bytes, "workspace_bytes": adj.ws_bytes, "kernels": kernels}
 
 
+def sharp_lf_leg(steps=20, warmup=3, tile=-1):
+    """The 4096x4096 circles workload as configured, with sharp point-sampled regions, on the LF flux
+    (which runs it; GKS meets a non-physical state after 3 steps there, as the oracle does)."""
+    import torch
+    from paper_2402_10914_amd import api
+    from paper_2402_10914_amd import workloads as WL
+    prob = WL.circles(4096, seed=10914, flux=WL.FLUX_LF, cfl=0.4, nsteps=50, edge_cells=0)
+    params = api.Params(flux=api.FLUX_LF, cfl=0.4, tile=max(tile, 0))
+    st = api.Stepper.for_problem(prob, params) if tile >= 0 else api.Stepper.tuned(prob, params)
+    W0 = torch.tensor(prob.W, device="cuda")
+    A0 = torch.tensor(prob.alpha, device="cuda")
+    W, A = W0.clone(), A0.clone()
+    st.run(W, A, warmup)
+    W.copy_(W0)
+    A.copy_(A0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, fail = st.run(W, A, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    done = steps if fail == -1 else fail
+    return {"workload": "4096x4096 periodic density wave + 32 circles with sharp point-sampled edges (rho ratio "
+                        "<= 10, p ratio <= 1e3), LF, WENO-AO+DF, S2O4, CFL 0.4", "dtype": "f64",
+            "value": prob.nx * prob.ny * done / el, "unit": "cell-updates/s", "steps": steps,
+            "ms_per_step": el * 1e3 / steps, "fail_step": fail, "tile": st.params.tile}
+
+
 def copy_mode(args):
     import torch
     n = 1 << 26  # 64 Mi doubles = 512 MiB each way
@@ -240,6 +268,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-sharp", action="store_true", help="skip the sharp-edged LF run of the circles workload")
     ap.add_argument("--mode", default="step", choices=["step", "copy", "adjoint"])
     ap.add_argument("--time-limiter", action="store_true", help="the non-linear time limiter (the paper's GKS solver)")
     ap.add_argument("--ssprk3", action="store_true", help="SSP-RK3 time steps (the paper's LF solver; LF workloads)")
@@ -269,10 +298,10 @@ def main():
     default_form = not (tl or ts)
     if args.tile >= 0:
         params.tile = args.tile
+        st = api.Stepper.for_problem(prob, params, dtype)
     else:
-        from paper_2402_10914_amd import autotune
-        params.tile, _ = autotune.tune_grid(prob, params, dtype)
-    st = api.Stepper.for_problem(prob, params, dtype)
+        st = api.Stepper.tuned(prob, params, dtype)
+        params = st.params
     W0 = torch.tensor(prob.W, dtype=dtype, device="cuda")
     A0 = torch.tensor(prob.alpha, dtype=dtype, device="cuda")
     W = W0.clone()
@@ -354,6 +383,7 @@ def main():
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps, args.cpu_cells, tl, ts),
         "batched": None if args.no_batch else batch_compare(),
         "adjoint": None if args.no_adjoint else adjoint_compare(),
+        "sharp_edges_lf": None if (args.no_sharp or not args.workload.startswith("circles4096")) else sharp_lf_leg(),
     }
     print(json.dumps(out), flush=True)
     if fail != -1:

@@ -128,6 +128,15 @@ class Stepper:
     def for_problem(cls, prob, params: Params, dtype=torch.float64, device="cuda"):
         return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.bc_x, prob.bc_y, params, dtype, device)
 
+    @classmethod
+    def tuned(cls, prob, params: Params, dtype=torch.float64, device="cuda"):
+        """A Stepper with the interface tile shape the autotuner picks for this grid (timed on the
+        problem's own initial state, cached per GPU architecture, sizes and options; results do not
+        depend on the tile)."""
+        from . import autotune
+        tile, _ = autotune.tune_grid(prob, params, dtype)
+        return cls.for_problem(prob, Params(**{**params.__dict__, "tile": tile}), dtype, device)
+
     def _check(self, W: torch.Tensor, alpha: torch.Tensor | None = None):
         g = self.grid
         _require(W, "W", self.dtype, self.device, shape=(4, g.ny, g.nx))

@@ -170,7 +170,8 @@ def circles(n=4096, seed=10914, ncirc=32, edge_cells=2.0, gamma=GAMMA, flux=FLUX
     and later regions overwrite earlier ones by geometric blending:
         log q <- (1 - f) log q + f log q_region   (q = rho, p).
     The smooth edge keeps the initial WENO reconstruction from producing negative Gauss-point
-    pressures at the sharpest (pressure ratio 1e3) edges, which the scheme has no limiter for."""
+    pressures at the sharpest (pressure ratio 1e3) edges, which the scheme has no limiter for.
+    edge_cells = 0 gives the sharp, point-sampled regions (f = 1 where r <= R, else 0)."""
     rng = np.random.default_rng(seed)
     d = 2.0 / n
     xc = _centres(n, 0.0, d)[None, :]
@@ -188,7 +189,8 @@ def circles(n=4096, seed=10914, ncirc=32, edge_cells=2.0, gamma=GAMMA, flux=FLUX
         ddx = np.minimum(ddx, 2.0 - ddx)
         ddy = np.abs(yc - cy)
         ddy = np.minimum(ddy, 2.0 - ddy)
-        f = 0.5 * (1.0 - np.tanh((np.sqrt(ddx * ddx + ddy * ddy) - r) / w))
+        dist = np.sqrt(ddx * ddx + ddy * ddy)
+        f = (dist <= r).astype(np.float64) if edge_cells <= 0 else 0.5 * (1.0 - np.tanh((dist - r) / w))
         lrho = (1.0 - f) * lrho + f * np.log(rho_bg * rfac)
         lp = (1.0 - f) * lp + f * np.log(pin)
     rho = np.exp(lrho)

@@ -172,3 +172,23 @@ def test_failing_ragged_grid_matches_oracle_up_to_its_failure():
     assert fs == 1  # the 22nd step fails
     out = _batched([p, probs[160]], api.Params(flux=0, cfl=0.4), 100)
     assert out[0][3] == 22 and out[1][3] == -1
+
+
+def test_tuned_stepper_matches_default_tile(tmp_path, monkeypatch):
+    """Stepper.tuned picks a tile shape by timing the problem itself (cached); results are bitwise
+    those of the default tile."""
+    monkeypatch.setenv("DFW_TUNE_CACHE", str(tmp_path / "tune.json"))
+    api = _api()
+    pr = WL.riemann4(96, 80, seed=9)
+    params = api.Params(flux=api.FLUX_GKS, cfl=0.4)
+    st = api.Stepper.tuned(pr, params)
+    assert 0 <= st.params.tile < len(api.tile_shapes())
+    ref = api.Stepper.for_problem(pr, params)
+    outs = []
+    for s in (st, ref):
+        W = torch.tensor(pr.W, device="cuda")
+        A = torch.tensor(pr.alpha, device="cuda")
+        s.run(W, A, 6)
+        outs.append((W.cpu().numpy(), A.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert (tmp_path / "tune.json").exists()

@@ -232,6 +232,53 @@ def test_circles4096_fifty_steps_properties(flux, dtype):
     assert float(A.min()) < 0.5  # the blast edges engage the hybrid switch
 
 
+SHARP = os.path.join(os.path.dirname(__file__), "golden", "circles4096_sharp_gks.json")
+
+
+@pytest.mark.skipif(not os.path.exists(SHARP), reason="golden file not generated")
+def test_circles4096_sharp_edges_gks_fails_where_the_oracle_fails():
+    """The 4096x4096 circles workload with sharp, point-sampled regions (density ratios up to 10,
+    pressure ratios up to 1e3), GKS: the scheme has no positivity limiter, and the oracle meets
+    non-physical cell averages after 3 steps (stored by tests/golden/make_circles4096_sharp.py); the
+    GPU stops at the same step, at the same cells, after the same time steps."""
+    import json
+    ref = json.load(open(SHARP))
+    pr = WL.circles(4096, seed=10914, cfl=0.4, edge_cells=0)
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=api.FLUX_GKS, cfl=0.4))
+    W = torch.tensor(pr.W, device="cuda")
+    A = torch.tensor(pr.alpha, device="cuda")
+    n = ref["steps_requested"]
+    dth = torch.zeros(n, dtype=torch.float64, device="cuda")
+    t, fs = st.run(W, A, n, dt_hist=dth)
+    assert fs == ref["fail_step"] == 3
+    Wn = W.cpu().numpy()
+    p = 0.4 * (Wn[3] - 0.5 * (Wn[1] ** 2 + Wn[2] ** 2) / Wn[0])
+    bad = ~(np.isfinite(Wn).all(axis=0) & (Wn[0] > 0) & (p > 0))
+    assert sorted(map(list, zip(*np.nonzero(bad)))) == sorted(ref["nonphysical_cells"])
+    np.testing.assert_allclose(dth.cpu().numpy()[:fs], ref["dt_hist"][:fs], rtol=1e-12)
+    assert abs(t - ref["t"]) <= 1e-12 * ref["t"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_circles4096_sharp_edges_lf_runs_fifty_steps(dtype):
+    """The same sharp-edged workload with the LF flux survives the 50 steps in FP64 and FP32:
+    conservation on the periodic grid and DF in [0, 1]."""
+    pr = WL.circles(4096, seed=10914, cfl=0.4, edge_cells=0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=api.FLUX_LF, cfl=0.4), tdt)
+    W = torch.tensor(pr.W, dtype=tdt, device="cuda")
+    A = torch.tensor(pr.alpha, dtype=tdt, device="cuda")
+    s0 = W.double().sum(dim=(1, 2))
+    _, fs = st.run(W, A, 50)
+    assert fs == -1
+    s1 = W.double().sum(dim=(1, 2))
+    scale = W.double().abs().sum(dim=(1, 2))
+    assert float(((s1 - s0).abs() / scale).max()) <= (1e-12 if dtype == "f64" else 2e-5)
+    assert float(A.min()) >= 0.0 and float(A.max()) <= 1.0
+
+
 @pytest.mark.parametrize("kw,nsteps", [(dict(flux=WL.FLUX_GKS, time_limiter=1), 2),
                                        (dict(flux=WL.FLUX_LF, time_scheme=1), 3)])
 def test_riemann512_paper_solver_configurations_full_grid(kw, nsteps):
