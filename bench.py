@@ -117,20 +117,23 @@ def cpu_baseline(prob, steps, cells, time_limiter=0, time_scheme=0):
                       f"same flux and boundary types ({el:.1f} s, OpenMP over rows)"}
 
 
-def batch_compare(nsteps=100, tune=True):
-    """Ragged batch of 256 grids (LF, FP64): one captured-graph replay against the per-grid loop."""
+def batch_compare(nsteps=100, tune=True, dtype_name="f64"):
+    """Ragged batch of 256 grids (LF, FP64 or FP32): one captured-graph replay against the per-grid
+    loop, both with the tile and order the autotuner picks for the batch."""
     import torch
     from paper_2402_10914_amd import api, autotune
     from paper_2402_10914_amd import workloads as WL
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
     probs = WL.batch(256, seed=256, flux=WL.FLUX_LF, cfl=0.4, nsteps=nsteps)
     grids = [(p.nx, p.ny, p.dx, p.dy, p.bc_x, p.bc_y) for p in probs]
     params = api.Params(flux=api.FLUX_LF, cfl=0.4)
     tile, order = 0, 0
     if tune:
-        tile, order, _ = autotune.tune_batch(grids, [p.W for p in probs], [p.alpha for p in probs], params, steps=5)
+        tile, order, _ = autotune.tune_batch(grids, [p.W for p in probs], [p.alpha for p in probs], params, dtype,
+                                             steps=5)
         params = api.Params(flux=api.FLUX_LF, cfl=0.4, tile=tile)
     cells = sum(p.nx * p.ny for p in probs)
-    b = api.Batch(grids, params, torch.float64, order)
+    b = api.Batch(grids, params, dtype, order)
     W0, A0 = b.pack([p.W for p in probs], [p.alpha for p in probs])
     W, A = W0.clone(), A0.clone()
     b.run(W, A, nsteps, use_graph=True)  # capture
@@ -141,25 +144,24 @@ def batch_compare(nsteps=100, tune=True):
     _, fs = b.run(W, A, nsteps, use_graph=True)
     torch.cuda.synchronize()
     t_graph = time.perf_counter() - t0
-    steppers = [api.Stepper.for_problem(p, params) for p in probs]
-    Ws = [torch.tensor(p.W, device="cuda") for p in probs]
-    As = [torch.tensor(p.alpha, device="cuda") for p in probs]
+    steppers = [api.Stepper.for_problem(p, params, dtype) for p in probs]
+    Ws = [torch.tensor(p.W, dtype=dtype, device="cuda") for p in probs]
+    As = [torch.tensor(p.alpha, dtype=dtype, device="cuda") for p in probs]
     for st, w, a in zip(steppers, Ws, As):  # warm
         st.run(w.clone(), a.clone(), 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for st, w, a in zip(steppers, Ws, As):
-        st.run(w, a, nsteps)
+    fl = [st.run(w, a, nsteps)[1] for st, w, a in zip(steppers, Ws, As)]
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
     views = b.unpack(W, A)
     same = all(bool(torch.equal(torch.nan_to_num(v[0]), torch.nan_to_num(w))) and bool(torch.equal(torch.nan_to_num(v[1]), torch.nan_to_num(a))) for v, w, a in zip(views, Ws, As))
     # grids that meet a non-physical state stop there (in both forms): count executed updates only
     done = sum(p.nx * p.ny * (nsteps if f == -1 else f) for p, f in zip(probs, fs))
-    return {"grids": len(probs), "cells": cells, "steps": nsteps, "dtype": "f64", "flux": "lf",
+    return {"grids": len(probs), "cells": cells, "steps": nsteps, "dtype": dtype_name, "flux": "lf",
             "executed_cell_updates": done,
             "graph_cell_updates_per_s": done / t_graph, "loop_cell_updates_per_s": done / t_loop,
-            "speedup": t_loop / t_graph, "bitwise_equal": same, "tile": tile, "order": order,
+            "speedup": t_loop / t_graph, "bitwise_equal": same and list(fs) == fl, "tile": tile, "order": order,
             "graph_ms": t_graph * 1e3, "loop_ms": t_loop * 1e3, "failed_grids": sum(1 for f in fs if f != -1)}
 
 
@@ -382,6 +384,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, args.cpu_steps, args.cpu_cells, tl, ts),
         "batched": None if args.no_batch else batch_compare(),
+        "batched_f32": None if args.no_batch else batch_compare(dtype_name="f32"),
         "adjoint": None if args.no_adjoint else adjoint_compare(),
         "sharp_edges_lf": None if (args.no_sharp or not args.workload.startswith("circles4096")) else sharp_lf_leg(),
     }
