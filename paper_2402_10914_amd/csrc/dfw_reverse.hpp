@@ -74,37 +74,59 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   const Coef<real> k = make_coef<real, RULE>(S);
 
   // ---- stage cells (rows t0-4 .. t0+TR+3) and alpha in LDS, local component order; tiles whose halo
-  //      lies inside the grid skip the boundary index map (uniform over the workgroup)
+  //      lies inside the grid skip the boundary index map (uniform over the workgroup).  Every load is
+  //      issued before the first is waited for; threads past the end of a list reload its last entry
+  //      (in bounds) and store nothing.
+  constexpr int NWE = T::NQ * T::WN, NAE = T::NQ * T::AN;
+  constexpr int IW = (NWE + T::NT - 1) / T::NT, IA = (NAE + T::NT - 1) / T::NT;
   const bool inner = f0 - 3 >= 0 && f0 + T::WN - 3 <= Nn && t0 - 4 >= 0 && t0 + T::NQ - 4 <= Nt;
   auto map_n = [&](int i) { return inner ? i : bc_map(i, Nn, bcn); };
   auto map_t = [&](int i) { return inner ? i : bc_map(i, Nt, bct); };
-  for (int e = tid; e < T::NQ * T::WN; e += T::NT) {
-    int nl, tl;
+  auto split = [&](int e, int width, int& nl, int& tl) {
     if (dir == 0) {
-      tl = e / T::WN;
-      nl = e % T::WN;
+      tl = e / width;
+      nl = e % width;
     } else {
       nl = e / T::NQ;
       tl = e % T::NQ;
     }
-    const int n = map_n(f0 - 3 + nl), t = map_t(t0 - 4 + tl);
-    const size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
-    sW[0][tl][nl] = W[g];
-    sW[1][tl][nl] = W[(dir ? 2 : 1) * N + g];
-    sW[2][tl][nl] = W[(dir ? 1 : 2) * N + g];
-    sW[3][tl][nl] = W[3 * N + g];
+  };
+  auto gcell = [&](int n, int t) -> size_t { return dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t; };
+  real rw[IW][4], ra[IA];
+#pragma unroll
+  for (int it = 0; it < IW; ++it) {
+    int nl, tl;
+    split(min(tid + it * T::NT, NWE - 1), T::WN, nl, tl);
+    const size_t g = gcell(map_n(f0 - 3 + nl), map_t(t0 - 4 + tl));
+    rw[it][0] = W[g];
+    rw[it][1] = W[(dir ? 2 : 1) * N + g];
+    rw[it][2] = W[(dir ? 1 : 2) * N + g];
+    rw[it][3] = W[3 * N + g];
   }
-  for (int e = tid; e < T::NQ * T::AN; e += T::NT) {
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
     int nl, tl;
-    if (dir == 0) {
-      tl = e / T::AN;
-      nl = e % T::AN;
-    } else {
-      nl = e / T::NQ;
-      tl = e % T::NQ;
+    split(min(tid + it * T::NT, NAE - 1), T::AN, nl, tl);
+    ra[it] = alpha[gcell(map_n(f0 - 2 + nl), map_t(t0 - 4 + tl))];
+  }
+#pragma unroll
+  for (int it = 0; it < IW; ++it) {
+    const int e = tid + it * T::NT;
+    if (e < NWE) {
+      int nl, tl;
+      split(e, T::WN, nl, tl);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sW[c][tl][nl] = rw[it][c];
     }
-    const int n = map_n(f0 - 2 + nl), t = map_t(t0 - 4 + tl);
-    sA[tl][nl] = alpha[dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t];
+  }
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
+    const int e = tid + it * T::NT;
+    if (e < NAE) {
+      int nl, tl;
+      split(e, T::AN, nl, tl);
+      sA[tl][nl] = ra[it];
+    }
   }
   __syncthreads();
 

@@ -178,8 +178,6 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
     t0 = (b / ntf) * TR;
     lead_tile = blockIdx.x == 0;
   }
-  Ctrl* ctrl = ctrls + gi;
-  if (ctrl->fail_at <= step) return;
   const int nx = G.nx, ny = G.ny;
   const real* W = Wall + G.w_off;
   const real* alpha = Aall + G.a_off;
@@ -190,6 +188,51 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   const real inv_dn = real(dir ? G.inv_dy : G.inv_dx), inv_dt = real(dir ? G.inv_dx : G.inv_dy);
   const size_t N = (size_t)nx * ny;
   const int tid = threadIdx.x;
+
+  // ---- gather the tile's cells and alpha (ghost cells by index mapping) into registers, every load
+  //      issued before the first is waited for, and before the control block is read, so that the
+  //      tile's memory latency is paid once.  Component order local: 0 rho, 1 normal momentum,
+  //      2 tangential momentum, 3 energy.  Tiles whose halo lies inside the grid (all but the tiles
+  //      at the boundaries) skip the index map, whose periodic branch is an integer remainder per
+  //      index; the test is uniform over the workgroup.  Threads past the end of the list reload the
+  //      last entry (in bounds) and store nothing.
+  constexpr int NWE = T::NR * T::WN, NAE = T::NR * T::AN;
+  constexpr int IW = (NWE + T::NT - 1) / T::NT, IA = (NAE + T::NT - 1) / T::NT;
+  const bool inner = f0 - 3 >= 0 && f0 + T::WN - 3 <= Nn && t0 - 2 >= 0 && t0 + T::NR - 2 <= Nt;
+  auto map_n = [&](int i) { return inner ? i : bc_map(i, Nn, bcn); };
+  auto map_t = [&](int i) { return inner ? i : bc_map(i, Nt, bct); };
+  // LDS coordinates of list entry e over a patch of `width` cells along the normal: along the
+  // normal fastest for x-interfaces (rows of the grid), along the tangent fastest for y-interfaces
+  auto split = [&](int e, int width, int& nl, int& tl) {
+    if (dir == 0) {
+      tl = e / width;
+      nl = e % width;
+    } else {
+      nl = e / T::NR;
+      tl = e % T::NR;
+    }
+  };
+  auto gcell = [&](int n, int t) -> size_t { return dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t; };
+  real rw[IW][4], ra[IA];
+#pragma unroll
+  for (int it = 0; it < IW; ++it) {
+    int nl, tl;
+    split(min(tid + it * T::NT, NWE - 1), T::WN, nl, tl);
+    const size_t g = gcell(map_n(f0 - 3 + nl), map_t(t0 - 2 + tl));
+    rw[it][0] = W[g];
+    rw[it][1] = W[(dir ? 2 : 1) * N + g];
+    rw[it][2] = W[(dir ? 1 : 2) * N + g];
+    rw[it][3] = W[3 * N + g];
+  }
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
+    int nl, tl;
+    split(min(tid + it * T::NT, NAE - 1), T::AN, nl, tl);
+    ra[it] = alpha[gcell(map_n(f0 - 2 + nl), map_t(t0 - 2 + tl))];
+  }
+
+  Ctrl* ctrl = ctrls + gi;
+  if (ctrl->fail_at <= step) return;
 
   // ---- dt of this step.  The first launch of a step computes it (every tile the same value: t and
   // the speed slot do not change during this launch) and records it; later launches read it.  With
@@ -215,41 +258,25 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
   const real dt = real(dtd);
   const Coef<real> k = make_coef<real>(S);
 
-  // ---- stage cells and alpha into LDS (ghost cells by index mapping); component order local:
-  //      0 rho, 1 normal momentum, 2 tangential momentum, 3 energy.  Tiles whose halo lies inside the
-  //      grid (all but the tiles at the boundaries) skip the index map, whose periodic branch is an
-  //      integer remainder per index; the test is uniform over the workgroup.
-  const bool inner = f0 - 3 >= 0 && f0 + T::WN - 3 <= Nn && t0 - 2 >= 0 && t0 + T::NR - 2 <= Nt;
-  auto map_n = [&](int i) { return inner ? i : bc_map(i, Nn, bcn); };
-  auto map_t = [&](int i) { return inner ? i : bc_map(i, Nt, bct); };
-  for (int e = tid; e < T::NR * T::WN; e += T::NT) {
-    int nl, tl;
-    if (dir == 0) {
-      tl = e / T::WN;
-      nl = e % T::WN;
-    } else {
-      nl = e / T::NR;
-      tl = e % T::NR;
+  // ---- the gathered tile into LDS
+#pragma unroll
+  for (int it = 0; it < IW; ++it) {
+    const int e = tid + it * T::NT;
+    if (e < NWE) {
+      int nl, tl;
+      split(e, T::WN, nl, tl);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sW[c][tl][nl] = rw[it][c];
     }
-    int n = map_n(f0 - 3 + nl), t = map_t(t0 - 2 + tl);
-    size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
-    sW[0][tl][nl] = W[g];
-    sW[1][tl][nl] = W[(dir ? 2 : 1) * N + g];
-    sW[2][tl][nl] = W[(dir ? 1 : 2) * N + g];
-    sW[3][tl][nl] = W[3 * N + g];
   }
-  for (int e = tid; e < T::NR * T::AN; e += T::NT) {
-    int nl, tl;
-    if (dir == 0) {
-      tl = e / T::AN;
-      nl = e % T::AN;
-    } else {
-      nl = e / T::NR;
-      tl = e % T::NR;
+#pragma unroll
+  for (int it = 0; it < IA; ++it) {
+    const int e = tid + it * T::NT;
+    if (e < NAE) {
+      int nl, tl;
+      split(e, T::AN, nl, tl);
+      sA[tl][nl] = ra[it];
     }
-    int n = map_n(f0 - 2 + nl), t = map_t(t0 - 2 + tl);
-    size_t g = dir == 0 ? (size_t)t * nx + n : (size_t)n * nx + t;
-    sA[tl][nl] = alpha[g];
   }
   __syncthreads();
 
