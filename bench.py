@@ -165,16 +165,17 @@ def batch_compare(nsteps=100, tune=True, dtype_name="f64"):
             "graph_ms": t_graph * 1e3, "loop_ms": t_loop * 1e3, "failed_grids": sum(1 for f in fs if f != -1)}
 
 
-def adjoint_compare(n=1024, nsteps=100, every=10):
-    """Adjoint workload (FP64, n x n periodic density wave plus 16 Gaussian bumps, LF, CFL 0.5,
-    nsteps steps, checkpoint every `every` steps, loss = L2 misfit of the final density to a seeded
-    target): time of the gradient (segment recomputation and reverse sweep) over the time of the
-    plain forward rollout."""
+def adjoint_compare(n=1024, nsteps=100, every=10, flux="lf"):
+    """Adjoint workload (FP64, n x n periodic density wave plus 16 Gaussian bumps, LF (or GKS),
+    CFL 0.5, nsteps steps, checkpoint every `every` steps, loss = L2 misfit of the final density to a
+    seeded target): time of the gradient (segment recomputation and reverse sweep) over the time of
+    the plain forward rollout."""
     import torch
     from paper_2402_10914_amd import api
     from paper_2402_10914_amd import workloads as WL
     prob = WL.bumps(n, seed=1024, cfl=0.5, nsteps=nsteps)
-    st = api.Stepper.for_problem(prob, api.Params(flux=api.FLUX_LF, cfl=0.5))
+    fl = {"lf": api.FLUX_LF, "gks": api.FLUX_GKS}[flux]
+    st = api.Stepper.for_problem(prob, api.Params(flux=fl, cfl=0.5))
     W0 = torch.tensor(prob.W, device="cuda")
     A0 = torch.tensor(prob.alpha, device="cuda")
     adj = api.Adjoint(st, nsteps, every)
@@ -206,7 +207,7 @@ def adjoint_compare(n=1024, nsteps=100, every=10):
                for k, (ms, c) in prof.items() if c}
     recompute_ms = sum(prof[k][0] for k in ("faces1", "update1", "faces2", "update2"))
     reverse_ms = sum(prof[k][0] for k in ("adj_faces1", "adj_faces2", "adj_gather"))
-    return {"grid": f"{n}x{n}", "steps": nsteps, "ckpt_every": every, "flux": "lf", "dtype": "f64",
+    return {"grid": f"{n}x{n}", "steps": nsteps, "ckpt_every": every, "flux": flux, "dtype": "f64",
             "forward_ms": round(t_fwd * 1e3, 2), "forward_with_checkpoints_ms": round(t_fwd_ckpt * 1e3, 2),
             "gradient_ms": round(t_bwd * 1e3, 2), "ratio_gradient_over_forward": round(t_bwd / t_fwd, 3),
             "recompute_kernels_ms": round(recompute_ms, 2), "reverse_kernels_ms": round(reverse_ms, 2),
@@ -274,6 +275,7 @@ def main():
     ap.add_argument("--mode", default="step", choices=["step", "copy", "adjoint"])
     ap.add_argument("--time-limiter", action="store_true", help="the non-linear time limiter (the paper's GKS solver)")
     ap.add_argument("--ssprk3", action="store_true", help="SSP-RK3 time steps (the paper's LF solver; LF workloads)")
+    ap.add_argument("--adjoint-flux", default="lf", choices=["lf", "gks"], help="flux of --mode adjoint")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -284,7 +286,7 @@ def main():
     if args.mode == "copy":
         return copy_mode(args)
     if args.mode == "adjoint":
-        print(json.dumps({"mode": "adjoint", **adjoint_compare()}))
+        print(json.dumps({"mode": "adjoint", **adjoint_compare(flux=args.adjoint_flux)}))
         return
 
     import torch
