@@ -165,11 +165,13 @@ def batch_compare(nsteps=100, tune=True, dtype_name="f64"):
             "graph_ms": t_graph * 1e3, "loop_ms": t_loop * 1e3, "failed_grids": sum(1 for f in fs if f != -1)}
 
 
-def adjoint_compare(n=1024, nsteps=100, every=10, flux="lf"):
+def adjoint_compare(n=1024, nsteps=100, every=10, flux="lf", tape=True):
     """Adjoint workload (FP64, n x n periodic density wave plus 16 Gaussian bumps, LF (or GKS),
     CFL 0.5, nsteps steps, checkpoint every `every` steps, loss = L2 misfit of the final density to a
     seeded target): time of the gradient (segment recomputation and reverse sweep) over the time of
-    the plain forward rollout."""
+    the plain forward rollout.  With `tape`, also the same with a checkpoint at every step (the
+    forward run keeps each step's whole record, the gradient recomputes nothing), and whether its
+    gradient equals the first bitwise."""
     import torch
     from paper_2402_10914_amd import api
     from paper_2402_10914_amd import workloads as WL
@@ -207,12 +209,28 @@ def adjoint_compare(n=1024, nsteps=100, every=10, flux="lf"):
                for k, (ms, c) in prof.items() if c}
     recompute_ms = sum(prof[k][0] for k in ("faces1", "update1", "faces2", "update2"))
     reverse_ms = sum(prof[k][0] for k in ("adj_faces1", "adj_faces2", "adj_gather"))
-    return {"grid": f"{n}x{n}", "steps": nsteps, "ckpt_every": every, "flux": flux, "dtype": "f64",
+    ckpt_bytes, ws_bytes = adj.ckpt_bytes, adj.ws_bytes
+    full = None
+    if tape:
+        del adj
+        torch.cuda.empty_cache()
+        adj1 = api.Adjoint(st, nsteps, 1)
+        W, A = W0.clone(), A0.clone()
+        t_fwd1, _ = timed(lambda: adj1.forward(W, A))
+        adj1.backward(gW, None)  # warm
+        t_bwd1, (gW1, _) = timed(lambda: adj1.backward(gW, None))
+        full = {"ckpt_every": 1, "forward_with_record_ms": round(t_fwd1 * 1e3, 2),
+                "gradient_ms": round(t_bwd1 * 1e3, 2), "ratio_gradient_over_forward": round(t_bwd1 / t_fwd, 3),
+                "checkpoint_bytes": adj1.ckpt_bytes, "workspace_bytes": adj1.ws_bytes,
+                "gradient_bitwise_equal": bool(torch.equal(gW1, gW0))}
+        del adj1
+        torch.cuda.empty_cache()
+    return {"grid": f"{n}x{n}", "steps": nsteps, "ckpt_every": every, "flux": flux, "dtype": "f64", "full_record": full,
             "forward_ms": round(t_fwd * 1e3, 2), "forward_with_checkpoints_ms": round(t_fwd_ckpt * 1e3, 2),
             "gradient_ms": round(t_bwd * 1e3, 2), "ratio_gradient_over_forward": round(t_bwd / t_fwd, 3),
             "recompute_kernels_ms": round(recompute_ms, 2), "reverse_kernels_ms": round(reverse_ms, 2),
             "loss": loss, "grad_norm": float(gW0.norm()), "fail_step": fs,
-            "checkpoint_bytes": adj.ckpt_bytes, "workspace_bytes": adj.ws_bytes, "kernels": kernels}
+            "checkpoint_bytes": ckpt_bytes, "workspace_bytes": ws_bytes, "kernels": kernels}
 
 
 def sharp_lf_leg(steps=20, warmup=3, tile=-1):

@@ -191,8 +191,11 @@ void dfw_batch_free(dfw_batch* b);
  * switch of eq. (42) contributes no derivative (the branch taken is differentiated).
  *
  * Memory: dfw_run_ckpt stores (W, alpha) at every ckpt_every-th step; dfw_adjoint recomputes one
- * segment of ckpt_every steps at a time from its checkpoint and reverses it.  The adjoint is FP64
- * (dtype DFW_F64; DFW_F32 gives DFW_EDTYPE).  Deterministic: no atomics, results are bitwise
+ * segment of ckpt_every steps at a time from its checkpoint and reverses it.  ckpt_every = 1 stores
+ * each step's whole record instead (W^n, alpha^n, the first-stage state W* and the second-stage
+ * interface DF products: about 11 N values per step, N = nx ny), and dfw_adjoint recomputes
+ * nothing; the gradient is bitwise the same for every ckpt_every.  The adjoint is FP64 (dtype
+ * DFW_F64; DFW_F32 gives DFW_EDTYPE).  Deterministic: no atomics, results are bitwise
  * reproducible. */
 
 /* Bytes of the checkpoint store of an nsteps rollout (0 for invalid arguments). */
@@ -205,7 +208,8 @@ dfw_status dfw_run_ckpt(void* W, void* alpha, const dfw_grid* grid, const dfw_pa
                         int32_t dtype, int32_t ckpt_every, void* ckpt, size_t ckpt_bytes, void* ws,
                         size_t ws_bytes, double* dt_hist_dev, double* t_out, int32_t* fail_step, void* stream);
 
-/* Workspace bytes of dfw_adjoint (0 for invalid arguments); about (11 ckpt_every + 70) N values. */
+/* Workspace bytes of dfw_adjoint (0 for invalid arguments); about (11 ckpt_every + 70) N values,
+ * 70 N for ckpt_every = 1. */
 size_t dfw_adjoint_workspace_bytes(const dfw_grid* grid, int32_t dtype, int32_t ckpt_every);
 
 /* Adjoint of the rollout recorded by dfw_run_ckpt (same grid, params, nsteps, ckpt_every; ckpt and

@@ -267,7 +267,10 @@ class Adjoint:
         t, fail_step = adj.forward(W, alpha)           # in place; records checkpoints and dt
         gW0, gA0 = adj.backward(gW_N, gA_N)            # dJ/dW^0, dJ/dalpha^0 at the recorded dt
 
-    The time steps are held at the recorded values (the CFL reduction is not differentiated)."""
+    The time steps are held at the recorded values (the CFL reduction is not differentiated).
+    ckpt_every = 1 records each step whole (about 11 values per cell and step: 9.2 GB for 100 steps
+    of a 1024 x 1024 grid) and backward recomputes nothing; the gradient is bitwise the same for
+    every ckpt_every."""
 
     def __init__(self, stepper: Stepper, nsteps: int, ckpt_every: int = 10):
         if stepper.dtype != torch.float64:

@@ -533,17 +533,29 @@ static void launch_adj_faces(const real* W, const real* A, const real* P, const 
                        dim3(2 * TF * (TR + 4)), 0, st, W, A, P, Q, LA, DX, DY, BX, BY, G, S, dt_hist, step);
 }
 
-// Checkpoint store: one slot per segment of ckpt_every steps, slot = W (4N) | alpha (N).
+// Checkpoint store: one slot per segment of ckpt_every steps, slot = W (4N) | alpha (N).  With a
+// checkpoint at every step (ckpt_every = 1) the slot is the whole record of its step, W^n | alpha^n |
+// W* | stage-2 DF products of the x and the y interfaces, and the adjoint recomputes nothing.
 struct CkptLayout {
-  size_t w_off, a_off, slot, total;
+  size_t w_off, a_off, ws_off, dfx_off, dfy_off, slot, total;
+  bool tape;
 };
 
 static CkptLayout ckpt_layout(const dfw_grid* g, size_t es, int nsteps, int every) {
   CkptLayout L;
   const size_t N = (size_t)g->nx * g->ny;
+  const size_t sx = (size_t)g->ny * (g->nx + 1), sy = (size_t)(g->ny + 1) * g->nx;
+  L.tape = every == 1;
   L.w_off = 0;
   L.a_off = align256(4 * N * es);
   L.slot = L.a_off + align256(N * es);
+  L.ws_off = L.dfx_off = L.dfy_off = 0;
+  if (L.tape) {
+    L.ws_off = L.slot;
+    L.dfx_off = L.ws_off + align256(4 * N * es);
+    L.dfy_off = L.dfx_off + align256(sx * es);
+    L.slot = L.dfy_off + align256(sy * es);
+  }
   const int nseg = nsteps > 0 ? (nsteps + every - 1) / every : 0;
   L.total = (size_t)nseg * L.slot;
   return L;
@@ -561,6 +573,7 @@ static AdjLayout adj_layout(const dfw_grid* g, size_t es, int every) {
   L.fwd = layout(g, es);
   const size_t N = (size_t)g->nx * g->ny;
   const size_t sx = (size_t)g->ny * (g->nx + 1), sy = (size_t)(g->ny + 1) * g->nx;
+  if (every == 1) every = 0;  // the checkpoint store holds every step's record: nothing is recomputed
   L.wN = align256(4 * N * es) / es;
   L.aN = align256(N * es) / es;
   L.sx = align256(sx * es) / es;
@@ -591,7 +604,8 @@ static AdjLayout adj_layout(const dfw_grid* g, size_t es, int every) {
 }
 
 // Forward steps with checkpoints: the ordinary enqueue with a copy of (W, alpha) into slot n/every
-// before every step n that starts a segment.
+// before every step n that starts a segment; with ckpt_every = 1 also the W* and the stage-2 DF
+// products of step n (still in the workspace until step n + 1 starts) into slot n.
 template <class real>
 static dfw_status run_ckpt_impl(real* W, real* A, const dfw_grid* g, const dfw_params* p, int nsteps, int every,
                                 char* ckpt, char* ws, double* dt_hist, double* t_out, int32_t* fail_step,
@@ -602,7 +616,21 @@ static dfw_status run_ckpt_impl(real* W, real* A, const dfw_grid* g, const dfw_p
   CkptLayout C = ckpt_layout(g, es, nsteps, every);
   Ctrl* ctrl = (Ctrl*)(ws + L.ctrl_off);
   const GridDesc G = make_desc(g);
+  const size_t sx = (size_t)g->ny * (g->nx + 1), sy = (size_t)(g->ny + 1) * g->nx;
+  auto record = [&](int n) -> hipError_t {  // tape: the intermediates of step n
+    char* slot = ckpt + (size_t)n * C.slot;
+    hipError_t e = hipMemcpyAsync(slot + C.ws_off, ws + L.ws_off, 4 * N * es, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(slot + C.dfx_off, ws + L.fx_off + 8 * sx * es, sx * es, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(slot + C.dfy_off, ws + L.fy_off + 8 * sy * es, sy * es, hipMemcpyDeviceToDevice, st);
+    return e;
+  };
   auto hook = [&](int n) -> hipError_t {
+    if (C.tape && n > 0) {
+      hipError_t e = record(n - 1);
+      if (e != hipSuccess) return e;
+    }
     if (n % every) return hipSuccess;
     char* slot = ckpt + (size_t)(n / every) * C.slot;
     hipError_t e = hipMemcpyAsync(slot + C.w_off, W, 4 * N * es, hipMemcpyDeviceToDevice, st);
@@ -615,6 +643,7 @@ static dfw_status run_ckpt_impl(real* W, real* A, const dfw_grid* g, const dfw_p
                       nullptr, (int)cell_blocks(G), p, nsteps, dt_hist, st, [&](int n) {
                         if (he == hipSuccess) he = hook(n);
                       });
+  if (he == hipSuccess && C.tape && nsteps > 0) he = record(nsteps - 1);
   HIP_TRY(he);
   HIP_TRY(hipGetLastError());
   Ctrl h;
@@ -681,6 +710,24 @@ static dfw_status adjoint_impl(const dfw_grid* g, const dfw_params* p, int nstep
     const real* A0 = (const real*)(slot + C.a_off);
     auto Wn = [&](int l) { return l == 0 ? W0 : (const real*)Wst(l); };
     auto An = [&](int l) { return l == 0 ? A0 : (const real*)Ast(l); };
+    if (C.tape) {  // one step, recorded whole by the forward run: reverse it directly
+      real* Wsl = (real*)(slot + C.ws_off);
+      real* DXl = (real*)(slot + C.dfx_off);
+      real* DYl = (real*)(slot + C.dfy_off);
+      timed(DFW_K_ADJ_FACES2, st, [&] {
+        launch_adj_faces<real, FLUX, 2>(Wsl, A0, LW, nullptr, LA, DXl, DYl, BX, BY, G, S, dt_hist, n0, st);
+      });
+      timed(DFW_K_ADJ_GATHER, st, [&] {
+        hipLaunchKernelGGL((k_adj_gather<real, 2>), dim3(nb), dim3(kCellBlock), 0, st, BX, BY, LW, LWs, LA, G);
+      });
+      timed(DFW_K_ADJ_FACES1, st, [&] {
+        launch_adj_faces<real, FLUX, 1>(W0, A0, LWs, LW, nullptr, nullptr, nullptr, BX, BY, G, S, dt_hist, n0, st);
+      });
+      timed(DFW_K_ADJ_GATHER, st, [&] {
+        hipLaunchKernelGGL((k_adj_gather<real, 1>), dim3(nb), dim3(kCellBlock), 0, st, BX, BY, LW, LWs, LA, G);
+      });
+      continue;
+    }
     // recompute the segment, keeping W^n, alpha^n, W* and the stage-2 DF products of every step
     for (int n = n0; n < n1; ++n) {
       const int l = n - n0;

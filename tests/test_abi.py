@@ -113,6 +113,22 @@ def test_rhs_and_speed_validation_without_gpu():
                            None) == _lib.DFW_EINVAL
 
 
+def test_full_tape_sizes_without_gpu():
+    """ckpt_every = 1 keeps each step's whole record (W^n, alpha^n, W*, the stage-2 DF products of
+    the x and the y interfaces, each region 256-byte aligned) and no recomputation buffers."""
+    L = _lib.load()
+    nx, ny, n = 37, 23, 5
+    g = _grid(nx, ny)
+    a = lambda b: (b + 255) // 256 * 256
+    N, sx, sy = nx * ny, ny * (nx + 1), (ny + 1) * nx
+    rec = a(4 * N * 8) + a(N * 8) + a(4 * N * 8) + a(sx * 8) + a(sy * 8)
+    assert L.dfw_checkpoint_bytes(ctypes.byref(g), 0, n, 1) == n * rec
+    assert L.dfw_checkpoint_bytes(ctypes.byref(g), 0, n, 2) == 3 * (a(4 * N * 8) + a(N * 8))
+    ws1 = L.dfw_adjoint_workspace_bytes(ctypes.byref(g), 0, 1)
+    ws2 = L.dfw_adjoint_workspace_bytes(ctypes.byref(g), 0, 2)
+    assert ws2 - ws1 == 2 * (2 * a(4 * N * 8) + a(N * 8) + a(sx * 8) + a(sy * 8))
+
+
 def test_adjoint_validation_without_gpu():
     """dfw_adjoint validates before any device work: FP32, the time limiter, a missing dt history
     and a small checkpoint store are rejected; the size queries are host-only."""
