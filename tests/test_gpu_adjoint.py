@@ -233,6 +233,32 @@ def test_deterministic_and_independent_of_checkpoint_interval():
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), every
 
 
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+def test_full_record_equals_checkpointed_gradient_on_bumps64(flux):
+    """ckpt_every = 1 (each step recorded whole by the forward run, nothing recomputed) against
+    checkpoints every ten steps on the 64x64 instance of the adjoint workload, 100 steps: the same
+    final state and the same gradient (W and alpha), bit for bit."""
+    nsteps = 100
+    pr, dt, target = _bumps_loss_setup(64, nsteps)
+    api = _api()
+    st = api.Stepper.for_problem(pr, api.Params(flux=flux, dt_fixed=dt))
+    area = pr.dx * pr.dy
+    out = []
+    for every in (10, 1):
+        adj = api.Adjoint(st, nsteps, every)
+        W = torch.tensor(pr.W, device="cuda")
+        A = torch.tensor(pr.alpha, device="cuda")
+        _, fs = adj.forward(W, A)
+        assert fs == -1
+        gW = torch.zeros_like(W)
+        gW[0] = area * (W[0] - torch.tensor(target, device="cuda"))
+        gW0, gA0 = adj.backward(gW, torch.ones_like(A))
+        out.append([x.cpu().numpy() for x in (W, A, gW0, gA0)])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    assert np.abs(out[0][2]).max() > 0
+
+
 def test_zero_steps_is_identity():
     pr = WL.riemann4(9, 11, seed=2)
     gW, gA = _seeds(pr, 1)
