@@ -190,7 +190,6 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
 
   // ---- segment forward, this side: states at the two Gauss points
   const bool seg = face && t >= 0 && t < Nt;
-  const Basis<real> B = basis_row(rr + 2);
   real al[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) al[q] = sA[rr + 1 + q][fl + 1 + side];
@@ -200,7 +199,10 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   for (int g = 0; g < 2; ++g)
 #pragma unroll
     for (int c = 0; c < 4; ++c) gw[g][c] = gwt[g][c] = real(0);
-  if (seg) segment_side<RULE>(B, line, al, inv_dt, k, gw, gwt);
+  // the segment's basis is rebuilt from LDS at each use (here, in the segment reverse and in the
+  // normal-sweep reverse) rather than held across the phases in between: 20 fewer live values there,
+  // 32-48 fewer bytes of spills per lane
+  if (seg) segment_side<RULE>(basis_row(rr + 2), line, al, inv_dt, k, gw, gwt);
 
   // ---- adjoints of the face sums from the cell seeds (face f: -1/dn to cell f-1, +1/dn to cell f)
   const int cmap[4] = {0, dir ? 2 : 1, dir ? 1 : 2, 3};
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   real la_seg = real(0);
   if (seg) {
     auto ll_add = [&](int m, int c, real v) { ll[m][c] += v; };
-    segment_side_adj<RULE>(B, line, al, inv_dt, k, lgw, lgwt, ll_add, lB, la_seg);
+    segment_side_adj<RULE>(basis_row(rr + 2), line, al, inv_dt, k, lgw, lgwt, ll_add, lB, la_seg);
   }
   real acc[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -355,8 +357,8 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   if (own) {
     auto cell = [&](int m, int c) -> real { return sW[c][rr + 2][fl + (side ? 5 - m : m)]; };
     auto lc_add = [&](int m, int c, real v) { lcs[m][c] += v; };
-    normal_side_adj<RULE>(B, cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc, lwn, lc_add, lB,
-                          la_ns);
+    normal_side_adj<RULE>(basis_row(rr + 2), cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc,
+                          lwn, lc_add, lB, la_ns);
   }
   // basis adjoint of the pair (side 0 first on both lanes), then the two cells it is built from
   BasisAdj<real> lBt;
