@@ -56,7 +56,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   __shared__ real sW[4][T::NQ][T::WN];
   __shared__ real sA[T::NQ][T::AN];
   __shared__ real sL[4][2 * TF * T::NQ];  // line values, the two sides of a segment side by side
-  __shared__ real sX[4][T::NT];            // exchange of line adjoints between rows
+  __shared__ real sX[5][4][T::NT];         // exchange of line adjoints between rows (m = 0..4)
 
   int b = blockIdx.x;
   const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
@@ -329,19 +329,20 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
     auto ll_add = [&](int m, int c, real v) { ll[m][c] += v; };
     segment_side_adj<RULE>(basis_row(rr + 2), line, al, inv_dt, k, lgw, lgwt, ll_add, lB, la_seg);
   }
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sX[m][c][tid] = ll[m][c];
+  __syncthreads();
   real acc[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sX[c][tid] = ll[m][c];
-    __syncthreads();
     const int src = rr + 2 - m;  // the segment whose line m is this pair's row
     if (src >= 0 && src < T::NR) {
       const int st = 2 * pidx(fl, src) + side;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] += sX[c][st];
+      for (int c = 0; c < 4; ++c) acc[c] += sX[m][c][st];
     }
-    __syncthreads();
   }
 
   // ---- normal-sweep adjoint of the rows this tile owns: its TR rows, the two ghost rows below the
