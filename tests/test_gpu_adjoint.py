@@ -259,8 +259,9 @@ def test_full_record_equals_checkpointed_gradient_on_bumps64(flux):
     assert np.abs(out[0][2]).max() > 0
 
 
-def test_zero_steps_is_identity():
+@pytest.mark.parametrize("every", [10, 1])
+def test_zero_steps_is_identity(every):
     pr = WL.riemann4(9, 11, seed=2)
     gW, gA = _seeds(pr, 1)
-    gW0, gA0, _, _ = _gpu_grad(pr, WL.FLUX_LF, 1e-3, 0, 10, gW, gA)
+    gW0, gA0, _, _ = _gpu_grad(pr, WL.FLUX_LF, 1e-3, 0, every, gW, gA)
     assert np.array_equal(gW0, gW) and np.array_equal(gA0, gA)
