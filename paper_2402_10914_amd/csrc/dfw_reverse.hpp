@@ -57,6 +57,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   __shared__ real sA[T::NQ][T::AN];
   __shared__ real sL[4][2 * TF * T::NQ];  // line values, the two sides of a segment side by side
   __shared__ real sX[5][4][T::NT];         // exchange of line adjoints between rows (m = 0..4)
+  __shared__ real sN[4][T::NT];            // each lane's normal-derivative adjoints, parked
 
   int b = blockIdx.x;
   const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   if (seg)
     gp_flux_adj<real, FLUX>(wl, wln, wlt, wr, wrn, wrt, dt, k, lFs, lFts, STAGE == 2 ? ldfp * df_other : real(0), lwl,
                             lwln, lwlt, lwr, lwrn, lwrt);
-  real lgw[2][4], lgwt[2][4], lwn[4];
+  real lgw[2][4], lgwt[2][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const real own = side ? lwr[c] : lwl[c], own_t = side ? lwrt[c] : lwlt[c], own_n = side ? lwrn[c] : lwln[c];
@@ -311,7 +312,9 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
     lgw[1][c] = side ? own : got;
     lgwt[0][c] = side ? got_t : own_t;
     lgwt[1][c] = side ? own_t : got_t;
-    lwn[c] = side ? got_n + own_n : own_n + got_n;  // Gauss point 0 first on both lanes
+    // Gauss point 0 first on both lanes; parked in the lane's own LDS slots until the normal-sweep
+    // reverse instead of being held (and spilled) through the segment reverse
+    sN[c][tid] = side ? got_n + own_n : own_n + got_n;
   }
   __syncthreads();  // the reverse reloads its LDS inputs after this point
 
@@ -358,6 +361,9 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
   if (own) {
     auto cell = [&](int m, int c) -> real { return sW[c][rr + 2][fl + (side ? 5 - m : m)]; };
     auto lc_add = [&](int m, int c, real v) { lcs[m][c] += v; };
+    real lwn[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lwn[c] = sN[c][tid];
     normal_side_adj<RULE>(basis_row(rr + 2), cell, a_of(rr + 2, 0), a_of(rr + 2, 1), a_of(rr + 2, 2), sgn_dn, k, acc,
                           lwn, lc_add, lB, la_ns);
   }
