@@ -74,6 +74,9 @@ struct GridDesc {
 struct Scheme {
   double gamma, cfl, dt_fixed, alpha_thres, eps, c1, c2, K;
   double d[4];
+  // derived on the host (the same IEEE operations), so that kernels receive them as arguments instead
+  // of computing them in vector registers, which they would hold for the whole launch
+  double gm1, inv_gm1, dr[3], inv_d3, K2, k4K2;
   int tl;  // non-linear time limiter (eqs. (27)-(29)) on
   int ts;  // time scheme: DFW_TIME_S2O4 (eq. (21)) or DFW_TIME_SSPRK3 (eq. (32))
   double t_end;  // > 0: stop at this time
@@ -92,18 +95,18 @@ template <class real, int RULE = -1>
 __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
   Coef<real> k;
   k.gamma = real(S.gamma);
-  k.gm1 = real(S.gamma - 1.0);
-  k.inv_gm1 = real(1.0 / (S.gamma - 1.0));
+  k.gm1 = real(S.gm1);
+  k.inv_gm1 = real(S.inv_gm1);
   k.alpha_thres = real(S.alpha_thres);
   k.eps = real(S.eps);
   k.c1 = real(S.c1);
   k.c2 = real(S.c2);
   k.K = real(S.K);
   for (int i = 0; i < 4; ++i) k.d[i] = real(S.d[i]);
-  for (int i = 0; i < 3; ++i) k.dr[i] = real(S.d[i] / S.d[3]);
-  k.inv_d3 = real(1.0 / S.d[3]);
-  k.K2 = real(S.K + 2.0);
-  k.k4K2 = real(4.0 / (S.K + 2.0));
+  for (int i = 0; i < 3; ++i) k.dr[i] = real(S.dr[i]);
+  k.inv_d3 = real(S.inv_d3);
+  k.K2 = real(S.K2);
+  k.k4K2 = real(S.k4K2);
   k.sw_rule = RULE >= 0 ? RULE : S.sw;
   return k;
 }
@@ -864,6 +867,12 @@ static Scheme make_scheme(const dfw_params* p) {
   S.d[0] = (1.0 - p->d_h) * (1.0 - p->d_l) / 2.0;
   S.d[1] = (1.0 - p->d_h) * p->d_l;
   S.d[2] = S.d[0];
+  S.gm1 = S.gamma - 1.0;
+  S.inv_gm1 = 1.0 / (S.gamma - 1.0);
+  for (int i = 0; i < 3; ++i) S.dr[i] = S.d[i] / S.d[3];
+  S.inv_d3 = 1.0 / S.d[3];
+  S.K2 = S.K + 2.0;
+  S.k4K2 = 4.0 / (S.K + 2.0);
   S.tl = p->time_limiter;
   S.ts = p->time_scheme;
   S.t_end = p->t_end;
