@@ -77,6 +77,7 @@ struct Scheme {
   // derived on the host (the same IEEE operations), so that kernels receive them as arguments instead
   // of computing them in vector registers, which they would hold for the whole launch
   double gm1, inv_gm1, dr[3], inv_d3, K2, k4K2;
+  Coef<float> k32;  // every coefficient rounded to FP32 on the host, for the FP32 kernels
   int tl;  // non-linear time limiter (eqs. (27)-(29)) on
   int ts;  // time scheme: DFW_TIME_S2O4 (eq. (21)) or DFW_TIME_SSPRK3 (eq. (32))
   double t_end;  // > 0: stop at this time
@@ -93,6 +94,11 @@ constexpr int kFacePlanes = 10;  // F (4), dF/dt (4), DF product, time-limiter w
 // RULE >= 0 fixes the hybrid switch rule at compile time; RULE < 0 takes the rule of S.
 template <class real, int RULE = -1>
 __device__ __forceinline__ Coef<real> make_coef(const Scheme& S) {
+  if constexpr (sizeof(real) == sizeof(float)) {
+    Coef<real> k = S.k32;
+    k.sw_rule = RULE >= 0 ? RULE : S.sw;
+    return k;
+  }
   Coef<real> k;
   k.gamma = real(S.gamma);
   k.gm1 = real(S.gm1);
@@ -119,6 +125,18 @@ constexpr int kXcds = 8;
 __host__ __device__ __forceinline__ int xcd_tile(int b, int n) {
   const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
   return x * q + (x < r ? x : r) + k;
+}
+
+// A value the same in every lane, moved to scalar registers (kernels at the register limit would
+// otherwise hold values computed by vector instructions in vector registers).
+__device__ __forceinline__ double uniform_value(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float uniform_value(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
 __device__ __forceinline__ int bc_map(int i, int n, int bc) {
@@ -258,7 +276,7 @@ __global__ __launch_bounds__(TF * (TR + 4)) void k_faces(const real* __restrict_
     }
   }
   if (!(dtd > 0.0)) return;  // uniform over the launch
-  const real dt = real(dtd);
+  const real dt = uniform_value(real(dtd));
   const Coef<real> k = make_coef<real>(S);
 
   // ---- the gathered tile into LDS
@@ -873,6 +891,21 @@ static Scheme make_scheme(const dfw_params* p) {
   S.inv_d3 = 1.0 / S.d[3];
   S.K2 = S.K + 2.0;
   S.k4K2 = 4.0 / (S.K + 2.0);
+  Coef<float>& f = S.k32;  // round to nearest, as a conversion on the device
+  f.gamma = float(S.gamma);
+  f.gm1 = float(S.gm1);
+  f.inv_gm1 = float(S.inv_gm1);
+  f.alpha_thres = float(S.alpha_thres);
+  f.eps = float(S.eps);
+  f.c1 = float(S.c1);
+  f.c2 = float(S.c2);
+  f.K = float(S.K);
+  for (int i = 0; i < 4; ++i) f.d[i] = float(S.d[i]);
+  for (int i = 0; i < 3; ++i) f.dr[i] = float(S.dr[i]);
+  f.inv_d3 = float(S.inv_d3);
+  f.K2 = float(S.K2);
+  f.k4K2 = float(S.k4K2);
+  f.sw_rule = p->switch_rule;
   S.tl = p->time_limiter;
   S.ts = p->time_scheme;
   S.t_end = p->t_end;
