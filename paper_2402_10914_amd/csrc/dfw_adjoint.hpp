@@ -1223,13 +1223,14 @@ DFW_HD void segment_side(const Basis<real>& B, LineFn line, const real* al, real
   }
 }
 
-// Reverse of segment_side for the adjoints lgw, lgwt of the Gauss-point states: the adjoints of the
-// side's line values go to ll_add(m, c, v); lB and la_c accumulate.  One characteristic component at a time, as in
-// normal_side_adj.
-template <int C, int RULE, class real, class LineFn, class AddFn>
-DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
-                                  const real (*lgw)[4], const real (*lgwt)[4], real lqv0, real lqv1, real lqd0,
-                                  real lqd1, AddFn ll_add, BasisAdj<real>& lB, real& la_c) {
+// Reverse of segment_side for the adjoints lgw, lgwt of the Gauss-point states, in two halves.
+// First half, one characteristic component at a time: the reverse of the Gauss-point
+// reconstruction gives the characteristic adjoints of the side's five line values, handed to
+// put_q(C, m, v) (component C, row m); lB and la_c accumulate.
+template <int C, int RULE, class real, class LineFn, class PutFn>
+DFW_HD void segment_side_adj_q_comp(const Basis<real>& B, LineFn line, const real* al, real inv_dt,
+                                    const Coef<real>& k, const real (*lgw)[4], const real (*lgwt)[4], real lqv0,
+                                    real lqv1, real lqd0, real lqd1, PutFn put_q, BasisAdj<real>& lB, real& la_c) {
   real s[5], lQc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -1246,30 +1247,53 @@ DFW_HD void segment_side_adj_comp(const Basis<real>& B, LineFn line, const real*
   unproject_adj_B_comp<C>(B, d[0] * inv_dt, lgwt[0], lB);
   unproject_adj_B_comp<C>(B, d[1] * inv_dt, lgwt[1], lB);
 #pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    real w[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) w[c] = line(m, c);
-    real d[4] = {0, 0, 0, 0};
-    project_adj_comp<C>(B, w, lQc[m], d, lB);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ll_add(m, c, d[c]);
-  }
+  for (int m = 0; m < 5; ++m) put_q(C, m, lQc[m]);
 }
 
-template <int RULE = -1, class real, class LineFn, class AddFn>
-DFW_HD void segment_side_adj(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
-                             const real (*lgw)[4], const real (*lgwt)[4], AddFn ll_add, BasisAdj<real>& lB,
-                             real& la_c) {
+template <int RULE = -1, class real, class LineFn, class PutFn>
+DFW_HD void segment_side_adj_q(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
+                               const real (*lgw)[4], const real (*lgwt)[4], PutFn put_q, BasisAdj<real>& lB,
+                               real& la_c) {
 #define DFW_SEG_COMP(C)                                                                                          \
-  segment_side_adj_comp<C, RULE>(B, line, al, inv_dt, k, lgw, lgwt, unproject_adj_q_comp<C>(B, lgw[0]),        \
-                           unproject_adj_q_comp<C>(B, lgw[1]), unproject_adj_q_comp<C>(B, lgwt[0]),            \
-                           unproject_adj_q_comp<C>(B, lgwt[1]), ll_add, lB, la_c)
+  segment_side_adj_q_comp<C, RULE>(B, line, al, inv_dt, k, lgw, lgwt, unproject_adj_q_comp<C>(B, lgw[0]),      \
+                                   unproject_adj_q_comp<C>(B, lgw[1]), unproject_adj_q_comp<C>(B, lgwt[0]),    \
+                                   unproject_adj_q_comp<C>(B, lgwt[1]), put_q, lB, la_c)
   DFW_SEG_COMP(0);
   DFW_SEG_COMP(1);
   DFW_SEG_COMP(2);
   DFW_SEG_COMP(3);
 #undef DFW_SEG_COMP
+}
+
+// Second half, one row at a time: the adjoint lw of line value w from the characteristic adjoints
+// lq[0..3] of its four components (the projection's reverse); lB accumulates.
+template <class real>
+DFW_HD void segment_side_adj_line(const Basis<real>& B, const real* w, const real* lq, real* lw, BasisAdj<real>& lB) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) lw[c] = real(0);
+  project_adj_comp<0>(B, w, lq[0], lw, lB);
+  project_adj_comp<1>(B, w, lq[1], lw, lB);
+  project_adj_comp<2>(B, w, lq[2], lw, lB);
+  project_adj_comp<3>(B, w, lq[3], lw, lB);
+}
+
+// The whole reverse: the adjoints of the side's line values go to ll_add(m, c, v); lB and la_c
+// accumulate.
+template <int RULE = -1, class real, class LineFn, class AddFn>
+DFW_HD void segment_side_adj(const Basis<real>& B, LineFn line, const real* al, real inv_dt, const Coef<real>& k,
+                             const real (*lgw)[4], const real (*lgwt)[4], AddFn ll_add, BasisAdj<real>& lB,
+                             real& la_c) {
+  real lQ[5][4];
+  segment_side_adj_q<RULE>(B, line, al, inv_dt, k, lgw, lgwt, [&](int C, int m, real v) { lQ[m][C] = v; }, lB, la_c);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    real w[4], d[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = line(m, c);
+    segment_side_adj_line(B, w, lQ[m], d, lB);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ll_add(m, c, d[c]);
+  }
 }
 
 // Reverse of the flux, its time derivative and the DF at one Gauss point (left state wl with normal

@@ -320,22 +320,38 @@ __global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
 
   // ---- segment reverse, this side: characteristic line adjoints, then the line adjoints of the
   //      five rows each segment reads, summed per row through LDS in a fixed order
+  //      In two halves: the reverse of the Gauss-point reconstruction, one characteristic component
+  //      at a time, parks the components' line adjoints in the lane's own slots of the exchange
+  //      buffer ([row][component]); after a barrier, which makes the compiler reload them rather
+  //      than hold 20 values through all four components, the projection's reverse turns each row's
+  //      four into that row's line adjoints in the same slots.
   BasisAdj<real> lB;
   lB.zero();
-  real ll[5][4];
-#pragma unroll
-  for (int m = 0; m < 5; ++m)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ll[m][c] = real(0);
   real la_seg = real(0);
+  if (seg)
+    segment_side_adj_q<RULE>(basis_row(rr + 2), line, al, inv_dt, k, lgw, lgwt,
+                             [&](int C, int m, real v) { sX[m][C][tid] = v; }, lB, la_seg);
+  __syncthreads();
   if (seg) {
-    auto ll_add = [&](int m, int c, real v) { ll[m][c] += v; };
-    segment_side_adj<RULE>(basis_row(rr + 2), line, al, inv_dt, k, lgw, lgwt, ll_add, lB, la_seg);
+    const Basis<real> B = basis_row(rr + 2);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      real w[4], lq[4], d[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        w[c] = line(m, c);
+        lq[c] = sX[m][c][tid];
+      }
+      segment_side_adj_line(B, w, lq, d, lB);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sX[m][c][tid] = d[c];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sX[m][c][tid] = real(0);
   }
-#pragma unroll
-  for (int m = 0; m < 5; ++m)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sX[m][c][tid] = ll[m][c];
   __syncthreads();
   real acc[4] = {0, 0, 0, 0};
 #pragma unroll
