@@ -46,8 +46,9 @@ __device__ __forceinline__ real pair_swap(real x) {
 // Thread 2p + s works on side s of interface segment p (s = 0: the cell before the interface).
 // RULE >= 0 fixes the hybrid switch rule at compile time (its selects fold away: this kernel is at
 // the register limit and pays for every live value); RULE < 0 reads the rule of S at run time.
+// The LF 2-interface tile asks for two waves per SIMD (see kAdjShapes).
 template <class real, int FLUX, int STAGE, int TF, int TR, int RULE>
-__global__ __launch_bounds__(2 * TF * (TR + 4)) void k_adj_faces(
+__global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) void k_adj_faces(
     const real* __restrict__ W, const real* __restrict__ alpha, const real* __restrict__ P,
     const real* __restrict__ Q, const real* __restrict__ LA, const real* __restrict__ DX,
     const real* __restrict__ DY, real* __restrict__ BX, real* __restrict__ BY, GridDesc G, Scheme S,
@@ -537,8 +538,11 @@ __global__ __launch_bounds__(kCellBlock) void k_fill(real* __restrict__ x, real 
 struct AdjShape {
   int tf, tr;
 };
-// Interface tiles of the adjoint kernel, per flux (LF, GKS).
-static constexpr AdjShape kAdjShapes[2] = {{4, 60}, {8, 12}};
+// Interface tiles of the adjoint kernel, per flux (LF, GKS).  The LF tile has 256 threads and is
+// held to two waves per SIMD (launch bounds), so that two workgroups share a compute unit and one's
+// barriers and staging overlap the other's arithmetic; the GKS kernel needs one wave per SIMD with
+// its accumulation registers as well.
+static constexpr AdjShape kAdjShapes[2] = {{2, 60}, {8, 12}};
 
 static int adj_tiles(int flux, int nx, int ny) {
   const AdjShape s = kAdjShapes[flux];
