@@ -852,12 +852,21 @@ DFW_HD void micro_slope_adj(const real* g, real U, real V, real lam, const Coef<
   llam += -K2 * real(0.5) * (ilam * ilam) * lB;
 }
 
-// Adjoint of gks_flux (lF may be null when the flux itself was not requested).
+// Adjoint of gks_flux (lF may be null when the flux itself was not requested), in two halves.  The first recomputes the flux and reverses its time
+// coefficients and the equilibrium-state part, down to the adjoints of the half-space sums
+// (Wc, Wcn, Wct, Flr, Malr) and the pressure-jump term of tau; the second reverses the two
+// half-space sides.  A caller short of registers can keep the handover in memory between them;
+// gks_flux_adj runs both in turn.
 template <class real>
-DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const real* wr, const real* wrn,
-                         const real* wrt, const Prim<real>& ql, const Prim<real>& qr, real dt, const Coef<real>& k,
-                         const real* lF, const real* lFt, real* lwl, real* lwln, real* lwlt, real* lwr, real* lwrn,
-                         real* lwrt, PrimAdj<real>& lql, PrimAdj<real>& lqr) {
+struct GksEqAdj {
+  real lWc[4], lWcn[4], lWct[4], lFlr[4], lMalr[4];
+  real lpl, lpr;  // the tau term's adjoints of the left and right pressure
+};
+
+template <class real>
+DFW_HD void gks_flux_adj_eq(const real* wln, const real* wlt, const real* wrn, const real* wrt, const Prim<real>& ql,
+                            const Prim<real>& qr, real dt, const Coef<real>& k, const real* lF, const real* lFt,
+                            GksEqAdj<real>& e) {
   // ---- forward recompute
   real Wc[4] = {0, 0, 0, 0}, Wcn[4] = {0, 0, 0, 0}, Wct[4] = {0, 0, 0, 0};
   real Flr[4] = {0, 0, 0, 0}, Malr[4] = {0, 0, 0, 0};
@@ -938,7 +947,10 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
   real cf1 = real(1) - tau * idt * z;
   real cf2 = tau * tau * idt * z + tau * (E1 - real(2) * E2);
   // ---- reverse: time coefficients
-  real lFc[4], lFlr[4], lMac[4], lMalr[4], lMAc[4];
+  real lFc[4], lMac[4], lMAc[4];
+  real* lFlr = e.lFlr;
+  real* lMalr = e.lMalr;
+  e.lpl = e.lpr = real(0);
   real lct1 = real(0), lct2 = real(0), lcf1 = real(0), lcf2 = real(0);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -971,13 +983,17 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
     real ltau = lct1 * dct1 + lct2 * dct2 + lcf1 * dcf1 + lcf2 * dcf2;
     real lpq = ltau * k.c2 * dt * sgn(pq);
     real isum = real(1) / (ql.p + qr.p);
-    lql.p += lpq * (real(1) - pq) * isum;
-    lqr.p += lpq * (real(-1) - pq) * isum;
+    e.lpl = lpq * (real(1) - pq) * isum;
+    e.lpr = lpq * (real(-1) - pq) * isum;
   }
   // ---- reverse: equilibrium-state fluxes
   MomAdj<real> lMc;
   lMc.zero();
-  real lWc[4] = {0, 0, 0, 0}, lWcn[4] = {0, 0, 0, 0}, lWct[4] = {0, 0, 0, 0};
+  real* lWc = e.lWc;
+  real* lWcn = e.lWcn;
+  real* lWct = e.lWct;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) lWc[c] = lWcn[c] = lWct[c] = real(0);
   real lac[4] = {0, 0, 0, 0}, lbc[4] = {0, 0, 0, 0}, lAc[4] = {0, 0, 0, 0};
   real lx[4], lfc[4], lxA[4];
 #pragma unroll
@@ -1022,6 +1038,20 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
   lWc[2] += lVc * irc;
   lirc += lUc * Wc[1] + lVc * Wc[2];
   lWc[0] += -lirc * irc * irc;
+}
+
+template <class real>
+DFW_HD void gks_flux_adj_sides(const real* wln, const real* wlt, const real* wrn, const real* wrt,
+                               const Prim<real>& ql, const Prim<real>& qr, const Coef<real>& k,
+                               const GksEqAdj<real>& e, real* lwln, real* lwlt, real* lwrn, real* lwrt,
+                               PrimAdj<real>& lql, PrimAdj<real>& lqr) {
+  const real* lWc = e.lWc;
+  const real* lWcn = e.lWcn;
+  const real* lWct = e.lWct;
+  const real* lFlr = e.lFlr;
+  const real* lMalr = e.lMalr;
+  lql.p += e.lpl;
+  lqr.p += e.lpr;
   // ---- reverse: the two half-space sides
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -1104,6 +1134,18 @@ DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const
     lq.r += llam * real(0.5) / q.p;
     lq.p += -llam * lam / q.p;
   }
+}
+
+template <class real>
+DFW_HD void gks_flux_adj(const real* wl, const real* wln, const real* wlt, const real* wr, const real* wrn,
+                         const real* wrt, const Prim<real>& ql, const Prim<real>& qr, real dt, const Coef<real>& k,
+                         const real* lF, const real* lFt, real* lwl, real* lwln, real* lwlt, real* lwr, real* lwrn,
+                         real* lwrt, PrimAdj<real>& lql, PrimAdj<real>& lqr) {
+  GksEqAdj<real> e;
+  gks_flux_adj_eq(wln, wlt, wrn, wrt, ql, qr, dt, k, lF, lFt, e);
+  gks_flux_adj_sides(wln, wlt, wrn, wrt, ql, qr, k, e, lwln, lwlt, lwrn, lwrt, lql, lqr);
+  (void)wl;
+  (void)wr;
   (void)lwl;
   (void)lwr;
 }

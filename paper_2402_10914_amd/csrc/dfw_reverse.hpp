@@ -59,6 +59,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
   __shared__ real sL[4][2 * TF * T::NQ];  // line values, the two sides of a segment side by side
   __shared__ real sX[5][4][T::NT];         // exchange of line adjoints between rows (m = 0..4)
   __shared__ real sN[4][T::NT];            // each lane's normal-derivative adjoints, parked
+  __shared__ real sE[FLUX == 1 ? 22 : 1][T::NT];  // the gas-kinetic reverse's hand-over, parked
 
   int b = blockIdx.x;
   const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
@@ -299,9 +300,61 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
   const real df_other = pair_swap(dfo);
   real lwl[4] = {0, 0, 0, 0}, lwln[4] = {0, 0, 0, 0}, lwlt[4] = {0, 0, 0, 0};
   real lwr[4] = {0, 0, 0, 0}, lwrn[4] = {0, 0, 0, 0}, lwrt[4] = {0, 0, 0, 0};
-  if (seg)
-    gp_flux_adj<real, FLUX>(wl, wln, wlt, wr, wrn, wrt, dt, k, lFs, lFts, STAGE == 2 ? ldfp * df_other : real(0), lwl,
-                            lwln, lwlt, lwr, lwrn, lwrt);
+  const real ldf = STAGE == 2 ? ldfp * df_other : real(0);
+  if constexpr (FLUX == 0) {
+    if (seg) gp_flux_adj<real, FLUX>(wl, wln, wlt, wr, wrn, wrt, dt, k, lFs, lFts, ldf, lwl, lwln, lwlt, lwr, lwrn, lwrt);
+  } else {
+    // The gas-kinetic reverse in two halves around a barrier: the Gauss point's 24 states and the 22
+    // values handed from the equilibrium-state reverse to the side reverse wait in the lane's own
+    // LDS slots (the exchange buffers are free until the segment reverse), so that neither half
+    // holds the other's live values; the barrier makes the compiler reload them.
+    GksEqAdj<real> e{};
+    if (seg) gks_flux_adj_eq(wln, wlt, wrn, wrt, prim(wl, k), prim(wr, k), dt, k, lFs, lFts, e);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sX[0][c][tid] = wl[c];
+      sX[1][c][tid] = wr[c];
+      sX[2][c][tid] = wln[c];
+      sX[3][c][tid] = wrn[c];
+      sX[4][c][tid] = wlt[c];
+      sN[c][tid] = wrt[c];
+      sE[c][tid] = e.lWc[c];
+      sE[4 + c][tid] = e.lWcn[c];
+      sE[8 + c][tid] = e.lWct[c];
+      sE[12 + c][tid] = e.lFlr[c];
+      sE[16 + c][tid] = e.lMalr[c];
+    }
+    sE[20][tid] = e.lpl;
+    sE[21][tid] = e.lpr;
+    __syncthreads();
+    if (seg) {
+      real vl[4], vr[4], vln[4], vrn[4], vlt[4], vrt[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        vl[c] = sX[0][c][tid];
+        vr[c] = sX[1][c][tid];
+        vln[c] = sX[2][c][tid];
+        vrn[c] = sX[3][c][tid];
+        vlt[c] = sX[4][c][tid];
+        vrt[c] = sN[c][tid];
+        e.lWc[c] = sE[c][tid];
+        e.lWcn[c] = sE[4 + c][tid];
+        e.lWct[c] = sE[8 + c][tid];
+        e.lFlr[c] = sE[12 + c][tid];
+        e.lMalr[c] = sE[16 + c][tid];
+      }
+      e.lpl = sE[20][tid];
+      e.lpr = sE[21][tid];
+      const Prim<real> ql = prim(vl, k), qr = prim(vr, k);
+      PrimAdj<real> lql, lqr;
+      lql.zero();
+      lqr.zero();
+      gks_flux_adj_sides(vln, vlt, vrn, vrt, ql, qr, k, e, lwln, lwlt, lwrn, lwrt, lql, lqr);
+      df_factor_adj(ql, qr, ldf, lql, lqr);
+      prim_adj(vl, ql, k, lql, lwl);
+      prim_adj(vr, qr, k, lqr, lwr);
+    }
+  }
   real lgw[2][4], lgwt[2][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -538,11 +591,12 @@ __global__ __launch_bounds__(kCellBlock) void k_fill(real* __restrict__ x, real 
 struct AdjShape {
   int tf, tr;
 };
-// Interface tiles of the adjoint kernel, per flux (LF, GKS).  The LF tile has 256 threads and is
-// held to two waves per SIMD (launch bounds), so that two workgroups share a compute unit and one's
-// barriers and staging overlap the other's arithmetic; the GKS kernel needs one wave per SIMD with
-// its accumulation registers as well.
-static constexpr AdjShape kAdjShapes[2] = {{2, 60}, {8, 12}};
+// Interface tiles of the adjoint kernel, per flux (LF, GKS): 2 interfaces x 60 rows, 256 threads.
+// The 60-row tile recomputes the segment adjoint (the costly part, above all with the GKS flux) for
+// 64 segment rows per 60 owned.  The LF kernel is held to two waves per SIMD (launch bounds), so that
+// two workgroups share a compute unit and one's barriers and staging overlap the other's arithmetic;
+// the GKS kernel needs one wave per SIMD with its accumulation registers as well, and 121 KB of LDS.
+static constexpr AdjShape kAdjShapes[2] = {{2, 60}, {2, 60}};
 
 static int adj_tiles(int flux, int nx, int ny) {
   const AdjShape s = kAdjShapes[flux];
