@@ -5,7 +5,8 @@ finite differences.
   numbers through its plain FP64 step) along every unit direction gives each entry of
   dJ/d(W^0, alpha^0) for J = <gW, W^N> + <gA, alpha^N>.  Cases: smooth data, a DF field that puts
   part of the grid on the DF branch of eq. (42), transmissive boundaries, LF and GKS.
-* Dot-product test on larger grids: <grad J, v> against the oracle's directional derivative.
+* Dot-product test on larger grids: <grad J, v> against the oracle's directional derivative,
+  also on a grid that spans several adjoint tiles in both directions (seams and ragged tails).
 * Central differences (eps = 1e-6) of the HIP forward on the 64x64 instance of the adjoint
   workload (density wave plus Gaussian bumps, LF, CFL 0.5, 100 steps, loss = L2 misfit of the
   final density): 8 random unit directions, 8 coordinate directions and the gradient direction.
@@ -141,6 +142,42 @@ def test_dot_product_against_oracle_directional_derivative(flux):
         ref = _oracle_directional(pr, flux, dt, nsteps, vW, vA, gW, gA)
         got = float((gW0 * vW).sum() + (gA0 * vA).sum())
         assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)
+
+
+def _random_states(nx, ny, seed):
+    """Periodic grid of random cell states (no two neighbouring pressures equal, so no kink argument
+    sits at zero), a denser block, and alpha partly below the DF threshold."""
+    pr = WL.density_wave(nx, ny)
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.2 * rng.random((ny, nx))
+    p = 1.0 + 0.3 * rng.random((ny, nx))
+    rho[ny // 3: ny // 2, nx // 4: nx // 2] *= 3.0
+    p[ny // 3: ny // 2, nx // 4: nx // 2] *= 2.0
+    u = 1.0 + 0.2 * rng.standard_normal((ny, nx))
+    v = 0.5 + 0.2 * rng.standard_normal((ny, nx))
+    pr.W = np.stack([rho, rho * u, rho * v, p / (WL.GAMMA - 1.0) + 0.5 * rho * (u * u + v * v)])
+    pr.alpha = rng.uniform(0.1, 1.0, (ny, nx))
+    return pr
+
+
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+@pytest.mark.parametrize("case", ["transmissive", "periodic_df"])
+def test_dot_product_across_adjoint_tile_seams(case, flux):
+    # 126 x 67: the x-interfaces span two 60-row adjoint tiles (the second ragged, 7 rows) and the
+    # y-interfaces three (the last 6 columns), so segment rows on both sides of every seam and the
+    # tails are reversed by different workgroups and summed by the gather
+    pr = WL.riemann4(126, 67, seed=13) if case == "transmissive" else _random_states(126, 67, 14)
+    nsteps, every = 4, 3
+    dt = _dt_of(pr, 0.4)
+    gW, gA = _seeds(pr, 15)
+    gW0, gA0, _, _ = _gpu_grad(pr, flux, dt, nsteps, every, gW, gA)
+    rng = np.random.default_rng(16)
+    for _ in range(3):
+        vW = rng.standard_normal(pr.W.shape)
+        vA = rng.standard_normal(pr.alpha.shape)
+        ref = _oracle_directional(pr, flux, dt, nsteps, vW, vA, gW, gA)
+        got = float((gW0 * vW).sum() + (gA0 * vA).sum())
+        assert abs(got - ref) <= 1e-10 * abs(ref), (case, got, ref)
 
 
 def _bumps_loss_setup(n=64, nsteps=100):
