@@ -5,7 +5,8 @@
 // The adjoint of one stage operator (U, alpha) -> (L, dL/dt, alpha_new), for given adjoints of its
 // outputs, takes two kernels:
 //   k_adj_faces   one workgroup per interface tile (the forward tiling; x and y interfaces in one
-//                 launch).  It stages the cells and alpha with a 4-row tangential halo in LDS,
+//                 launch).  It stages the cells and alpha with a 4-row tangential halo in LDS, and
+//                 the seed terms of the cells beside its interfaces (formed once per cell),
 //                 recomputes the normal-sweep line values of TR+8 rows, runs the segment adjoint
 //                 (Gauss-point reconstruction, flux, DF) of TR+4 segment rows, sums for each row the
 //                 line adjoints of the five segments that read it (five LDS rounds in a fixed order),
@@ -112,6 +113,37 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
     split(min(tid + it * T::NT, NAE - 1), T::AN, nl, tl);
     ra[it] = alpha[gcell(map_n(f0 - 2 + nl), map_t(t0 - 4 + tl))];
   }
+  // The seed terms of the cells the segment rows read (the TF+1 cells beside the tile's interfaces,
+  // normal index f0-1 .. f0+TF-1, on the NR segment rows), formed once per cell at staging rather
+  // than by the four lanes that read each: stage 1 the face-sum adjoints L = dt/2 P + dt Q and
+  // Lt = dt^2/8 P + dt^2/6 Q (KS = 8 values per cell); stage 2 Lt = dt^2/3 P and the DF-product
+  // adjoints LA (D_n (D_t0 D_t1)) with D_n the product of the cell's face f-1 (it is cell a of
+  // interface f) or f+1 (cell b), D_t0, D_t1 those of its two faces across (KS = 6).  Their loads fly
+  // with the tile's; the terms wait in the exchange buffer, which is free until the segment reverse.
+  // Thread tid < NSC takes one cell; cells off the grid load clamped (unused) entries.
+  constexpr int KS = STAGE == 1 ? 8 : 6, NSC = T::NR * (TF + 1);
+  static_assert(NSC <= T::NT && KS * NSC <= 20 * T::NT, "seed staging does not fit the tile");
+  real* const sS = &sX[0][0][0];
+  const int scl = dir == 0 ? tid % (TF + 1) : tid / T::NR, stl = dir == 0 ? tid / (TF + 1) : tid % T::NR;
+  real rs[STAGE == 1 ? 8 : 9];
+  if (tid < NSC) {
+    const int n = min(max(f0 - 1 + scl, 0), Nn - 1), tt = min(max(t0 - 2 + stl, 0), Nt - 1);
+    const size_t g = gcell(n, tt), rx = (size_t)nx + 1;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) rs[kk] = P[kk * N + g];
+    if constexpr (STAGE == 1) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) rs[4 + kk] = Q[kk * N + g];
+    } else {
+      rs[4] = LA[g];
+      // faces across (x-interfaces: y-faces below, above; y-interfaces: x-faces left, right), then
+      // the faces along the normal before and after the cell
+      rs[5] = dir == 0 ? DY[(size_t)tt * nx + n] : DX[(size_t)n * rx + tt];
+      rs[6] = dir == 0 ? DY[(size_t)(tt + 1) * nx + n] : DX[(size_t)n * rx + tt + 1];
+      rs[7] = dir == 0 ? DX[(size_t)tt * rx + n] : DY[(size_t)n * nx + tt];
+      rs[8] = dir == 0 ? DX[(size_t)tt * rx + n + 1] : DY[(size_t)(n + 1) * nx + tt];
+    }
+  }
 #pragma unroll
   for (int it = 0; it < IW; ++it) {
     const int e = tid + it * T::NT;
@@ -130,6 +162,26 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
       split(e, T::AN, nl, tl);
       sA[tl][nl] = ra[it];
     }
+  }
+  if (tid < NSC) {  // [term][row][cell]
+    real v[KS];
+    if constexpr (STAGE == 1) {
+      const real h1 = real(0.5) * dt, h2 = dt * dt * real(0.125), r2 = dt * dt * real(1.0 / 6.0);
+#pragma unroll
+      for (int gc = 0; gc < 4; ++gc) {
+        v[gc] = h1 * rs[gc] + dt * rs[4 + gc];
+        v[4 + gc] = h2 * rs[gc] + r2 * rs[4 + gc];
+      }
+    } else {
+      const real r3 = dt * dt * real(1.0 / 3.0);
+#pragma unroll
+      for (int gc = 0; gc < 4; ++gc) v[gc] = r3 * rs[gc];
+      const real across = rs[5] * rs[6];
+      v[4] = rs[4] * (rs[7] * across);
+      v[5] = rs[4] * (rs[8] * across);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) sS[(kk * T::NR + stl) * (TF + 1) + scl] = v[kk];
   }
   __syncthreads();
 
@@ -212,33 +264,21 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
   real lFs[4] = {0, 0, 0, 0}, lFts[4] = {0, 0, 0, 0}, ldfp = real(0);
   if (seg) {
     const bool has_a = f >= 1, has_b = f < Nn;
-    const size_t ga = dir == 0 ? (size_t)t * nx + (f - 1) : (size_t)(f - 1) * nx + t;
-    const size_t gb = dir == 0 ? (size_t)t * nx + f : (size_t)f * nx + t;
+    // staged seed terms of cell a = f-1 (cell column fl) and b = f (fl + 1) on this row
+    auto sd = [&](int kk, int cl) { return sS[(kk * T::NR + rr) * (TF + 1) + cl]; };
     real lF[4], lFt[4];
     if (STAGE == 1) {
-      const real h1 = real(0.5) * dt, h2 = dt * dt * real(0.125), r2 = dt * dt * real(1.0 / 6.0);
 #pragma unroll
       for (int gc = 0; gc < 4; ++gc) {
-        real La = 0, Lb = 0, Lta = 0, Ltb = 0;
-        if (has_a) {
-          const real p = P[gc * N + ga], q = Q[gc * N + ga];
-          La = h1 * p + dt * q;
-          Lta = h2 * p + r2 * q;
-        }
-        if (has_b) {
-          const real p = P[gc * N + gb], q = Q[gc * N + gb];
-          Lb = h1 * p + dt * q;
-          Ltb = h2 * p + r2 * q;
-        }
+        const real La = has_a ? sd(gc, fl) : real(0), Lb = has_b ? sd(gc, fl + 1) : real(0);
+        const real Lta = has_a ? sd(4 + gc, fl) : real(0), Ltb = has_b ? sd(4 + gc, fl + 1) : real(0);
         lF[gc] = (Lb - La) * inv_dn;
         lFt[gc] = (Ltb - Lta) * inv_dn;
       }
     } else {
-      const real r3 = dt * dt * real(1.0 / 3.0);
 #pragma unroll
       for (int gc = 0; gc < 4; ++gc) {
-        const real Lta = has_a ? r3 * P[gc * N + ga] : real(0);
-        const real Ltb = has_b ? r3 * P[gc * N + gb] : real(0);
+        const real Lta = has_a ? sd(gc, fl) : real(0), Ltb = has_b ? sd(gc, fl + 1) : real(0);
         lF[gc] = real(0);
         lFt[gc] = (Ltb - Lta) * inv_dn;
       }
@@ -252,30 +292,10 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
     lFts[1] = real(0.5) * (dir ? lFt[2] : lFt[1]);
     lFts[2] = real(0.5) * (dir ? lFt[1] : lFt[2]);
     lFts[3] = real(0.5) * lFt[3];
-    // adjoint of the Gauss-point DF product: alpha_new of a cell is the product of its four faces
+    // adjoint of the Gauss-point DF product (alpha_new of a cell is the product of its four faces)
     if (STAGE == 2) {
-      const size_t rx = (size_t)nx + 1;
-      if (dir == 0) {
-        const int j = t;
-        if (has_a) {
-          const int i = f - 1;
-          ldfp += LA[(size_t)j * nx + i] * (DX[j * rx + i] * (DY[(size_t)j * nx + i] * DY[(size_t)(j + 1) * nx + i]));
-        }
-        if (has_b) {
-          const int i = f;
-          ldfp += LA[(size_t)j * nx + i] * (DX[j * rx + i + 1] * (DY[(size_t)j * nx + i] * DY[(size_t)(j + 1) * nx + i]));
-        }
-      } else {
-        const int i = t;
-        if (has_a) {
-          const int j = f - 1;
-          ldfp += LA[(size_t)j * nx + i] * (DY[(size_t)j * nx + i] * (DX[j * rx + i] * DX[j * rx + i + 1]));
-        }
-        if (has_b) {
-          const int j = f;
-          ldfp += LA[(size_t)j * nx + i] * (DY[(size_t)(j + 1) * nx + i] * (DX[j * rx + i] * DX[j * rx + i + 1]));
-        }
-      }
+      if (has_a) ldfp += sd(4, fl);
+      if (has_b) ldfp += sd(5, fl + 1);
     }
   }
 
@@ -306,10 +326,11 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
   } else {
     // The gas-kinetic reverse in two halves around a barrier: the Gauss point's 24 states and the 22
     // values handed from the equilibrium-state reverse to the side reverse wait in the lane's own
-    // LDS slots (the exchange buffers are free until the segment reverse), so that neither half
-    // holds the other's live values; the barrier makes the compiler reload them.
+    // LDS slots (the exchange buffers hold nothing else between the seeds and the segment reverse),
+    // so that neither half holds the other's live values; the barrier makes the compiler reload them.
     GksEqAdj<real> e{};
     if (seg) gks_flux_adj_eq(wln, wlt, wrn, wrt, prim(wl, k), prim(wr, k), dt, k, lFs, lFts, e);
+    __syncthreads();  // every lane has read its staged seeds from the exchange buffer
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       sX[0][c][tid] = wl[c];
