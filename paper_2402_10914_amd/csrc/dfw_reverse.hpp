@@ -62,7 +62,7 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
   __shared__ real sN[4][T::NT];            // each lane's normal-derivative adjoints, parked
   __shared__ real sE[FLUX == 1 ? 22 : 1][T::NT];  // the gas-kinetic reverse's hand-over, parked
 
-  int b = blockIdx.x;
+  int b = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD (and its L2)
   const int nbx = tiles_x<TF, TR>(G.nx, G.ny);
   const int dir = b < nbx ? 0 : 1;
   if (dir) b -= nbx;
