@@ -9,7 +9,9 @@ finite differences.
   also on a grid that spans several adjoint tiles in both directions (seams and ragged tails).
 * Central differences (eps = 1e-6) of the HIP forward on the 64x64 instance of the adjoint
   workload (density wave plus Gaussian bumps, LF, CFL 0.5, 100 steps, loss = L2 misfit of the
-  final density): 8 random unit directions, 8 coordinate directions and the gradient direction.
+  final density): 8 random unit directions, 8 coordinate directions and the gradient direction;
+  and at the workload's full size (1024x1024, the benchmark's configuration): 3 random, 2
+  coordinate and the gradient direction.
 * Test data keep every kink argument away from zero (|p_l - p_r|, the LF speed max): at an exact
   kink the subgradient each side takes is decided by rounding.
 * Rollout (torch.autograd.Function), bitwise determinism, independence of the checkpoint
@@ -195,9 +197,13 @@ def _loss(api, st, W0, A0, nsteps, target_t, area):
     return 0.5 * area * float(((W[0] - target_t) ** 2).sum())
 
 
-def test_central_differences_on_bumps64():
+def _central_differences(n, n_random, n_coord, seed):
+    """The adjoint workload's loss on an n x n instance (density wave plus Gaussian bumps, LF, CFL 0.5,
+    100 steps, checkpoints every 10): the gradient against central differences (eps = 1e-6) of the HIP
+    forward along n_random random unit directions, n_coord coordinate directions spread over the
+    large entries, and the gradient direction."""
     nsteps, eps = 100, 1e-6
-    pr, dt, target = _bumps_loss_setup(64, nsteps)
+    pr, dt, target = _bumps_loss_setup(n, nsteps)
     api = _api()
     st = api.Stepper.for_problem(pr, api.Params(flux=api.FLUX_LF, dt_fixed=dt))
     W0 = torch.tensor(pr.W, device="cuda")
@@ -212,13 +218,13 @@ def test_central_differences_on_bumps64():
     gW[0] = area * (W[0] - tt)
     gW0, _ = adj.backward(gW, None)
     g = gW0.cpu().numpy()
-    rng = np.random.default_rng(64)
+    rng = np.random.default_rng(seed)
     dirs = []
-    for _ in range(8):
+    for _ in range(n_random):
         v = rng.standard_normal(pr.W.shape)
         dirs.append(v / np.linalg.norm(v))
     flat = np.argsort(np.abs(g).ravel())[::-1]
-    for k in flat[:: max(1, len(flat) // 64)][:8]:  # coordinate directions spread over the large entries
+    for k in flat[:: max(1, len(flat) // 64)][:n_coord]:  # coordinate directions spread over the large entries
         v = np.zeros(pr.W.size)
         v[k] = 1.0
         dirs.append(v.reshape(pr.W.shape))
@@ -227,13 +233,28 @@ def test_central_differences_on_bumps64():
     # relative to the directional derivative; for directions nearly orthogonal to the gradient the
     # rounding floor of the differences (about eps_mach J / eps) dominates, hence the floor at 1%
     # of |grad J| (a unit direction's derivative is at most |grad J|)
+    worst = 0.0
     for v in dirs:
         vt = torch.tensor(v, device="cuda")
         jp = _loss(api, st, W0 + eps * vt, A0, nsteps, tt, area)
         jm = _loss(api, st, W0 - eps * vt, A0, nsteps, tt, area)
         fd = (jp - jm) / (2 * eps)
         ad = float((g * v).sum())
-        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-2 * gnorm), (fd, ad, gnorm)
+        scale = max(abs(ad), 1e-2 * gnorm)
+        assert abs(fd - ad) <= 1e-6 * scale, (n, fd, ad, gnorm)
+        worst = max(worst, abs(fd - ad) / scale)
+    print(f"bumps{n} central differences: {len(dirs)} directions, worst relative difference {worst:.2e}", flush=True)
+
+
+def test_central_differences_on_bumps64():
+    _central_differences(64, 8, 8, 64)
+
+
+def test_central_differences_at_full_size_1024():
+    # the adjoint benchmark's grid, steps, checkpoint interval and launch configuration; the pressure
+    # of this workload is uniform, so the GKS collision time's |p_l - p_r| sits at its kink, where
+    # differences and the subgradient part ways: LF only
+    _central_differences(1024, 3, 2, 1024)
 
 
 def test_rollout_autograd_function_and_gradcheck():
