@@ -292,12 +292,14 @@ def test_deterministic_and_independent_of_checkpoint_interval():
 
 
 @pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
-def test_full_record_equals_checkpointed_gradient_on_bumps64(flux):
+@pytest.mark.parametrize("n", [64, 1024])
+def test_full_record_equals_checkpointed_gradient(n, flux):
     """ckpt_every = 1 (each step recorded whole by the forward run, nothing recomputed) against
-    checkpoints every ten steps on the 64x64 instance of the adjoint workload, 100 steps: the same
-    final state and the same gradient (W and alpha), bit for bit."""
+    checkpoints every ten steps on the n x n instance of the adjoint workload, 100 steps (n = 1024:
+    its full size, 9.2 GB of records): the same final state and the same gradient (W and alpha), bit
+    for bit."""
     nsteps = 100
-    pr, dt, target = _bumps_loss_setup(64, nsteps)
+    pr, dt, target = _bumps_loss_setup(n, nsteps)
     api = _api()
     st = api.Stepper.for_problem(pr, api.Params(flux=flux, dt_fixed=dt))
     area = pr.dx * pr.dy
