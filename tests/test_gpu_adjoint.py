@@ -4,7 +4,8 @@ finite differences.
 * Whole gradient, element by element, on tiny grids: the oracle's forward-mode derivative (dual
   numbers through its plain FP64 step) along every unit direction gives each entry of
   dJ/d(W^0, alpha^0) for J = <gW, W^N> + <gA, alpha^N>.  Cases: smooth data, a DF field that puts
-  part of the grid on the DF branch of eq. (42), transmissive boundaries, LF and GKS.
+  part of the grid on the DF branch of eq. (42), transmissive boundaries, LF and GKS; and on grids
+  narrower than the stencils (1x9 and 9x1 transmissive strips, a periodic 2x3 grid).
 * Dot-product test on larger grids: <grad J, v> against the oracle's directional derivative,
   also on a grid that spans several adjoint tiles in both directions (seams and ragged tails).
 * Central differences (eps = 1e-6) of the HIP forward on the 64x64 instance of the adjoint
@@ -128,6 +129,38 @@ def test_whole_gradient_matches_oracle_forward_mode(case, flux):
     assert _rel_l1(gA0, oA) <= 1e-10
     if case == "df":  # the DF branch carries derivative to alpha^0 through the blend
         assert np.abs(oA).max() > 1e-3
+
+
+def _degenerate(case):
+    rng = np.random.default_rng(73)
+    if case == "strip_x":  # one cell wide along x, transmissive
+        pr = WL.riemann4(1, 9, seed=8)
+    elif case == "strip_y":  # one cell high along y, transmissive
+        pr = WL.riemann4(9, 1, seed=8)
+    elif case == "periodic_2x3":  # smaller than every stencil in both directions, periodic
+        pr = WL.density_wave(2, 3)
+        pr.W = pr.W * (1.0 + 0.01 * rng.standard_normal(pr.W.shape))
+    else:
+        raise ValueError(case)
+    pr.alpha = rng.uniform(0.1, 1.0, (pr.ny, pr.nx))  # some cells on the DF branch
+    return pr
+
+
+@pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
+@pytest.mark.parametrize("case", ["strip_x", "strip_y", "periodic_2x3"])
+def test_whole_gradient_on_degenerate_grids(case, flux):
+    # grids narrower than the stencils: ghost cells fold back through the boundary map many times,
+    # in the tile staging, the seed staging and the gather
+    pr = _degenerate(case)
+    nsteps, every = 3, 2
+    dt = _dt_of(pr, 0.4)
+    gW, gA = _seeds(pr, 7)
+    gW0, gA0, _, _ = _gpu_grad(pr, flux, dt, nsteps, every, gW, gA)
+    oW, oA = _oracle_full_grad(pr, flux, dt, nsteps, gW, gA)
+    assert _rel_l1(gW0, oW) <= 1e-10, (case, _rel_l1(gW0, oW))
+    assert _rel_l1(gA0, oA) <= 1e-10, (case, _rel_l1(gA0, oA))
+    if case == "periodic_2x3":  # the DF branch carries derivative to alpha^0 (the strips' data are
+        assert np.abs(oA).max() > 1e-3  # constant along the DF-branch stencils)
 
 
 @pytest.mark.parametrize("flux", [WL.FLUX_LF, WL.FLUX_GKS])
