@@ -185,17 +185,12 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
   }
   __syncthreads();
 
+  // pair pr = rr * TF + fl in both directions: the TF interfaces of a segment row sit in adjacent
+  // lane pairs (one lane quad for TF = 2)
   const int side = tid & 1, pr = tid >> 1;
-  int fl, rr;
-  if (dir == 0) {
-    fl = pr % TF;
-    rr = pr / TF;
-  } else {
-    rr = pr % T::NR;
-    fl = pr / T::NR;
-  }
-  auto lidx = [&](int q, int c) { return dir == 0 ? q * TF + c : c * T::NQ + q; };
-  auto pidx = [&](int c, int r) { return dir == 0 ? r * TF + c : c * T::NR + r; };
+  const int fl = pr % TF, rr = pr / TF;
+  auto lidx = [&](int q, int c) { return q * TF + c; };
+  auto pidx = [&](int c, int r) { return r * TF + c; };
   const int f = f0 + fl;
   const int t = t0 - 2 + rr;  // segment row of this pair
   const bool face = f <= Nn;
