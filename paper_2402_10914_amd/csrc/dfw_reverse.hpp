@@ -10,20 +10,21 @@
 //                 recomputes the normal-sweep line values of TR+8 rows, runs the segment adjoint
 //                 (Gauss-point reconstruction, flux, DF) of TR+4 segment rows, sums for each row the
 //                 line adjoints of the five segments that read it (five LDS rounds in a fixed order),
-//                 runs the normal-sweep adjoint of the rows the tile owns, and writes per interface
-//                 and row the adjoints of the six cells of its normal stencil and of the two DFs it
-//                 reads: 26 values, each with exactly one writer (no atomics).
-//   k_adj_gather  one thread per cell: sums the interface-buffer entries whose stencil cell maps to
-//                 it (ghost cells fold back through the boundary map) in a fixed order, and applies
-//                 the stage recurrences of eq. (21) in reverse.
-// Results are bitwise reproducible and independent of the tile shape.
+//                 runs the normal-sweep adjoint of the rows the tile owns, and writes per row the
+//                 adjoints of the seven cells its two interfaces' normal stencils cover and of the
+//                 three DFs they read, the two interfaces' terms summed in the tile: 31 values, each
+//                 with exactly one writer (no atomics).
+//   k_adj_gather  one thread per cell: sums the window-buffer entries of the cell (ghost cells fold
+//                 back through the boundary map) in a fixed order, and applies the stage recurrences
+//                 of eq. (21) in reverse.
+// Results are bitwise reproducible.
 #pragma once
 
 #include "dfw_adjoint.hpp"
 
 namespace dfw {
 
-constexpr int kAdjSlots = 26;  // 6 stencil cells x 4 components, then the DF of cells f-1 and f
+constexpr int kAdjSlots = 31;  // per tile row: 7 stencil cells x 4 components, then 3 DF values
 
 template <int TF, int TR>
 struct AdjTile {
@@ -35,10 +36,30 @@ struct AdjTile {
   static constexpr int AN = TF + 3;   // alpha cells along the normal
 };
 
+// Value of lane (lane ^ X) within the lane's quad, X = 1, 2, 3, as two DPP quad permutes of the
+// 32-bit halves (vector moves, instead of a permute through the LDS unit).  Every lane of the quad
+// must be active.
+template <int X>
+__device__ __forceinline__ double quad_xor(double x) {
+  static_assert(X >= 1 && X <= 3, "a lane of the same quad");
+  // quad_perm selector: lane i of each quad reads lane i ^ X (two bits per lane)
+  constexpr int sel = (0 ^ X) | ((1 ^ X) << 2) | ((2 ^ X) << 4) | ((3 ^ X) << 6);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, sel, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), sel, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int X>
+__device__ __forceinline__ float quad_xor(float x) {
+  constexpr int sel = (0 ^ X) | ((1 ^ X) << 2) | ((2 ^ X) << 4) | ((3 ^ X) << 6);
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), sel, 0xF, 0xF, false));
+}
+
 // Value of the other lane of the pair (lanes 2p and 2p+1 hold the two sides of one segment).
 template <class real>
 __device__ __forceinline__ real pair_swap(real x) {
-  return __shfl_xor(x, 1);
+  return quad_xor<1>(x);
 }
 
 // STAGE 1: seeds lam_L = dt/2 P + dt Q, lam_Lt = dt^2/8 P + dt^2/6 Q (P = adjoint of W*, Q = of R).
@@ -474,53 +495,94 @@ __global__ __launch_bounds__(2 * TF * (TR + 4), (FLUX == 0 && TF == 2) ? 2 : 1) 
     }
   }
   // cells f-2+... : side 0 holds stencil cells 0..4 (lcs[m] = cell m), side 1 cells 5..1
-  // (lcs[m] = cell 5-m).  Lane 0 writes cells 0, 1, 2 and the DF of cell f-1; lane 1 cells 3, 4, 5
-  // and the DF of cell f.  Each lane needs the partner's lcs[3] and lcs[4].
+  // (lcs[m] = cell 5-m).  Lane 0 of a pair forms cells 0, 1, 2 and the DF of cell f-1; lane 1 cells
+  // 3, 4, 5 and the DF of cell f.  Each lane needs the partner's lcs[3] and lcs[4].
   real r3[4], r4[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     r3[c] = pair_swap(lcs[3][c]);
     r4[c] = pair_swap(lcs[4][c]);
   }
-  if (!own) return;
-  real lbc[4] = {0, 0, 0, 0}, lbc2[4] = {0, 0, 0, 0};
-  {
-    real wa[4], wb[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      wa[c] = sW[c][rr + 2][fl + 2];
-      wb[c] = sW[c][rr + 2][fl + 3];
-    }
-    make_basis_adj(wa, wb, k, lBt, lbc, lbc2);  // the same adjoint reaches both cells
-  }
-  real out[3][4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    if (side == 0) {
-      out[0][c] = lcs[0][c];
-      out[1][c] = lcs[1][c] + r4[c];
-      out[2][c] = (lcs[2][c] + r3[c]) + lbc[c];
-    } else {
-      out[0][c] = (r3[c] + lcs[2][c]) + lbc[c];
-      out[1][c] = r4[c] + lcs[1][c];
-      out[2][c] = lcs[0][c];
-    }
-  }
-  size_t sB;
-  real* o;
-  if (dir == 0) {
-    sB = (size_t)(ny + 4) * (nx + 1);
-    o = BX + (size_t)(t + 2) * (nx + 1) + f;
-  } else {
-    sB = (size_t)(ny + 1) * (nx + 4);
-    o = BY + (size_t)f * (nx + 4) + (t + 2);
-  }
-  const int m0 = 3 * side;
+  real out[3][4], dfv = real(0);
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) o[((m0 + m) * 4 + cmap[c]) * sB] = out[m][c];
-  o[(24 + side) * sB] = la_seg + la_ns;
+    for (int c = 0; c < 4; ++c) out[m][c] = real(0);
+  if (own) {
+    real lbc[4] = {0, 0, 0, 0}, lbc2[4] = {0, 0, 0, 0};
+    {
+      real wa[4], wb[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        wa[c] = sW[c][rr + 2][fl + 2];
+        wb[c] = sW[c][rr + 2][fl + 3];
+      }
+      make_basis_adj(wa, wb, k, lBt, lbc, lbc2);  // the same adjoint reaches both cells
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (side == 0) {
+        out[0][c] = lcs[0][c];
+        out[1][c] = lcs[1][c] + r4[c];
+        out[2][c] = (lcs[2][c] + r3[c]) + lbc[c];
+      } else {
+        out[0][c] = (r3[c] + lcs[2][c]) + lbc[c];
+        out[1][c] = r4[c] + lcs[1][c];
+        out[2][c] = lcs[0][c];
+      }
+    }
+    dfv = la_seg + la_ns;
+  }
+  // The tile's two interfaces of this row (lanes q = 0, 1: interface f0, sides 0, 1; q = 2, 3:
+  // interface f0+1) read overlapping stencils, cells f0-3 .. f0+2 and f0-2 .. f0+3: their cell
+  // adjoints are summed here into the row's window of seven cells w = 0..6 (cell f0-3+w) and three
+  // DF values d = 0..2 (cell f0-1+d), interface f0's term first; lanes that own no segment (rows
+  // outside the tile, an interface past the grid) add zeros.  With A = interface f0, B = f0+1 and
+  // [m] the m-th cell a side forms: lane q = side s of A writes w = 3s + m = A_s[m] + (B_s[m-1] for
+  // m = 1, 2; B_0[2] for s = 1, m = 0) and d = s = A_s + (B_0 for s = 1), the same code on both
+  // lanes; lane 3 writes w = 6 = B_1[2] and d = 2 = B_1.
+  static_assert(TF == 2, "the window of a tile row covers two interfaces");
+  real x2[2][4], x3[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    x2[0][c] = quad_xor<2>(out[0][c]);  // B_s on lane s (A's lanes)
+    x2[1][c] = quad_xor<2>(out[1][c]);
+    x3[c] = quad_xor<3>(out[2][c]);  // B_0[2] on lane 1
+  }
+  const real df3 = quad_xor<3>(dfv);                     // B_0's DF value on lane 1
+  const float own_a = quad_xor<2>(own ? 1.0f : 0.0f);   // on B's lanes: whether A owns the row
+  const bool row_own = fl == 0 ? own : own_a != 0.0f;
+  if (!row_own || (fl == 1 && side == 0)) return;
+  size_t sB, wfs, wrs;
+  real* o;
+  const int kt = f0 / TF;
+  if (dir == 0) {
+    const size_t nk = (size_t)(nx + 2) / 2;
+    sB = (size_t)(ny + 4) * nk;
+    wfs = 1;
+    wrs = nk;
+    o = BX;
+  } else {
+    const size_t nk = (size_t)(ny + 2) / 2;
+    sB = nk * (nx + 4);
+    wfs = (size_t)nx + 4;
+    wrs = 1;
+    o = BY;
+  }
+  o += (size_t)kt * wfs + (size_t)(t + 2) * wrs;
+  if (fl == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      o[((3 * side) * 4 + cmap[c]) * sB] = out[0][c] + (side ? x3[c] : real(0));
+      o[((3 * side + 1) * 4 + cmap[c]) * sB] = out[1][c] + x2[0][c];
+      o[((3 * side + 2) * 4 + cmap[c]) * sB] = out[2][c] + x2[1][c];
+    }
+    o[(28 + side) * sB] = dfv + (side ? df3 : real(0));
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[(6 * 4 + cmap[c]) * sB] = out[2][c];
+    o[30 * sB] = dfv;
+  }
 }
 
 // Indices in [lo, hi] that the boundary map sends to cell n of a line of Nn cells: a contiguous
@@ -543,25 +605,28 @@ __device__ __forceinline__ Preimages preimages(int n, int Nn, int bc, int lo, in
   return p;
 }
 
-// Sum of the interface-buffer entries of one direction that belong to cell (n, t) (normal,
-// tangential index).  Entry (f, row) at slot s sits at B[s*sB + f*fs + (row+2)*rs].
+// Sum of the window-buffer entries of one direction that belong to cell (n, t) (normal, tangential
+// index).  The window of tile k (interfaces 2k and 2k+1) and row `row` holds, at slot w*4 + c, the
+// adjoint of component c of cell 2k-3+w (w = 0..6), and at slot 28 + d that of the DF of cell
+// 2k-1+d (d = 0..2); it sits at B[slot*sB + k*fs + (row+2)*rs].  A cell is in the windows of three or
+// four tiles (its DF in one or two), summed in increasing k.
 template <class real>
 __device__ __forceinline__ void gather_dir(const real* __restrict__ B, size_t sB, size_t fs, size_t rs, int n, int Nn,
                                            int bcn, int t, int Nt, int bct, real* g, real& ga) {
+  const int nk = (Nn + 2) / 2;
   const Preimages pt = preimages(t, Nt, bct, -2, Nt + 1);
   const Preimages pn = preimages(n, Nn, bcn, -3, Nn + 2);
   for (int tp = pt.first; tp <= pt.last; tp += pt.stride) {
     const real* row = B + (size_t)(tp + 2) * rs;
     for (int e = pn.first; e <= pn.last; e += pn.stride) {
+      const int k0 = max((e - 2) >> 1, 0), k1 = min((e + 3) >> 1, nk - 1);  // floor division
+      for (int kk = k0; kk <= k1; ++kk) {
+        const int w = e - 2 * kk + 3;
 #pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const int f = e + 3 - m;
-        if (f < 0 || f > Nn) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) g[c] += row[(m * 4 + c) * sB + f * fs];
+        for (int c = 0; c < 4; ++c) g[c] += row[(w * 4 + c) * sB + kk * fs];
       }
-      if (e + 1 >= 0 && e + 1 <= Nn) ga += row[24 * sB + (e + 1) * fs];
-      if (e >= 0 && e <= Nn) ga += row[25 * sB + e * fs];
+      const int d0 = max(e >> 1, 0), d1 = min((e + 1) >> 1, nk - 1);
+      for (int kk = d0; kk <= d1; ++kk) ga += row[(28 + e - 2 * kk + 1) * sB + kk * fs];
     }
   }
 }
@@ -578,8 +643,9 @@ __global__ __launch_bounds__(kCellBlock) void k_adj_gather(const real* __restric
   if (o >= N) return;
   const int i = (int)(o % nx), j = (int)(o / nx);
   real g[4] = {0, 0, 0, 0}, ga = 0;
-  gather_dir(BX, (size_t)(ny + 4) * (nx + 1), 1, (size_t)nx + 1, i, nx, G.bc_x, j, ny, G.bc_y, g, ga);
-  gather_dir(BY, (size_t)(ny + 1) * (nx + 4), (size_t)nx + 4, 1, j, ny, G.bc_y, i, nx, G.bc_x, g, ga);
+  const size_t nkx = (size_t)(nx + 2) / 2, nky = (size_t)(ny + 2) / 2;
+  gather_dir(BX, (size_t)(ny + 4) * nkx, 1, nkx, i, nx, G.bc_x, j, ny, G.bc_y, g, ga);
+  gather_dir(BY, nky * (nx + 4), (size_t)nx + 4, 1, j, ny, G.bc_y, i, nx, G.bc_x, g, ga);
   if (STAGE == 2) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) LWs[c * N + o] = g[c];
@@ -694,10 +760,10 @@ static AdjLayout adj_layout(const dfw_grid* g, size_t es, int every) {
   off = align256(off + 4 * N * es);
   L.la = off;
   off = align256(off + N * es);
-  L.bx = off;
-  off = align256(off + (size_t)kAdjSlots * (g->ny + 4) * (g->nx + 1) * es);
+  L.bx = off;  // window buffers: kAdjSlots slots x rows x tiles of two interfaces
+  off = align256(off + (size_t)kAdjSlots * (g->ny + 4) * ((g->nx + 2) / 2) * es);
   L.by = off;
-  off = align256(off + (size_t)kAdjSlots * (g->ny + 1) * (g->nx + 4) * es);
+  off = align256(off + (size_t)kAdjSlots * ((g->ny + 2) / 2) * (g->nx + 4) * es);
   L.total = off;
   return L;
 }
