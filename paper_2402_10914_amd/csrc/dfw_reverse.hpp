@@ -726,7 +726,7 @@ static CkptLayout ckpt_layout(const dfw_grid* g, size_t es, int nsteps, int ever
   return L;
 }
 
-// Adjoint workspace: forward workspace | states of one segment | adjoint cells | interface buffers.
+// Adjoint workspace: forward workspace | states of one segment | adjoint cells | window buffers.
 struct AdjLayout {
   WsLayout fwd;
   size_t wst, ast, wss, dfx, dfy, lw, lws, la, bx, by, total;
